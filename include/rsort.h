@@ -1,0 +1,226 @@
+/*
+ * rsort -- robust sample sort for AMD MI355X (gfx950).
+ *
+ * C ABI of librsort.so.  Every data pointer is a DEVICE pointer owned by the
+ * caller unless stated otherwise; `stream` is a hipStream_t passed as void*
+ * (NULL = the null stream).  Calls return an int status (RSORT_OK = 0, or a
+ * negative error code); no exception crosses the ABI.
+ *
+ * Problem statement (paper, Section 2 "Preliminaries"): n input elements are
+ * to be output globally sorted.  Following the paper's robustness scheme
+ * (Section 5; Appendix F for the work-inefficient sort, Appendix G for the
+ * multi-level sample sort) keys are made unique by their input position, so
+ * the output is the unique permutation pi of 0..n-1 with
+ * (ord(x[pi(r)]), pi(r)) strictly increasing in r: ascending keys, equal keys
+ * in ascending input position.  ord is the identity for unsigned keys and the
+ * IEEE 754 totalOrder map for f32 keys (-NaN < -inf < ... < -0 < +0 < ... <
+ * +inf < +NaN; -0 and +0 are different keys).  Output keys keep their
+ * original bits.
+ *
+ * Asynchrony: rsort_plain and rsort_segmented enqueue work on `stream` and
+ * return without synchronising the host.  Argument errors detectable on the
+ * host are returned immediately; errors only detectable on the device (e.g.
+ * decreasing segment offsets) are recorded in the workspace status word and
+ * read back with rsort_workspace_status().
+ */
+#ifndef RSORT_H
+#define RSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { RSORT_U32 = 0, RSORT_U64 = 1, RSORT_F32 = 2 } rsort_key_t;
+
+enum {
+  RSORT_OK = 0,
+  RSORT_PENDING = 1,
+  RSORT_EINVAL = -1,   /* bad argument */
+  RSORT_ENOMEM = -2,   /* workspace too small / request larger than a budget */
+  RSORT_EDEVICE = -3,  /* HIP runtime or device error */
+  RSORT_EBUSY = -4,    /* server queue full */
+  RSORT_ENOTFOUND = -5 /* unknown ticket */
+};
+
+/* Static string for a status code. */
+const char *rsort_strerror(int code);
+
+/* ABI version (major * 100 + minor). */
+int rsort_version(void);
+
+/* ------------------------------------------------------------------------
+ * Plain sort (multilevel sample sort, paper Appendix G; single level for
+ * small n, plain LDS sort when n fits one workgroup).
+ *
+ * rsort_plain_workspace: bytes of device workspace rsort_plain needs for n
+ * keys of type kt (0 if kt is invalid).
+ *
+ * rsort_plain: sorts keys_in[0..n) into keys_out[0..n) and, if perm_out is
+ * not NULL, writes perm_out[r] = pi(r) (u32 input positions).
+ *   kt          key type; keys_in/keys_out hold 4-byte (u32, f32) or 8-byte
+ *               (u64) elements, contiguous.
+ *   n           0 <= n < 2^32 - 1; n == 0 is a no-op.
+ *   keys_out    must not overlap keys_in (out-of-place only).
+ *   workspace   device memory of at least rsort_plain_workspace(kt, n) bytes,
+ *               used only for the duration of the enqueued work.
+ * Errors: RSORT_EINVAL for a NULL pointer with n > 0, unknown kt, n too
+ * large, or overlapping buffers; RSORT_ENOMEM if workspace_bytes is too
+ * small; RSORT_EDEVICE if a launch fails.
+ * ---------------------------------------------------------------------- */
+size_t rsort_plain_workspace(rsort_key_t kt, uint64_t n);
+int rsort_plain(rsort_key_t kt, const void *keys_in, uint64_t n, void *keys_out, uint32_t *perm_out,
+                void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Segmented (batched) sort: num_segs independent arrays in one call, each
+ * sorted by the same definition with SEGMENT-LOCAL positions.  The work is a
+ * fixed sequence of launches independent of num_segs; each segment is routed
+ * to an algorithm by its size class (the paper's observation that different
+ * algorithms win at different input sizes, Section 4 and Section 7): the
+ * all-pairs rank sort RFIS (Section 5), robust quicksort RQuick (Section 6),
+ * an LDS merge sort, or multilevel sample-sort levels followed by the LDS
+ * sort of the final buckets.
+ *
+ *   seg_offsets  device array of num_segs + 1 u64: seg_offsets[0] = 0,
+ *                nondecreasing, seg_offsets[num_segs] = n_total; segment s
+ *                is [seg_offsets[s], seg_offsets[s+1]).  Segments must be
+ *                shorter than 2^32 - 1.  A decreasing offset sets the
+ *                workspace status to RSORT_EINVAL and leaves outputs undefined.
+ *   payload_in   optional (NULL) u32 values carried with the keys:
+ *                payload_out[r] = payload_in[start + pi_s(r - start)].
+ *   perm_out     optional (NULL): segment-local positions pi_s.
+ * Errors as for rsort_plain.
+ * ---------------------------------------------------------------------- */
+size_t rsort_segmented_workspace(rsort_key_t kt, uint64_t n_total, uint32_t num_segs,
+                                 int has_payload);
+int rsort_segmented(rsort_key_t kt, const void *keys_in, const uint32_t *payload_in,
+                    const uint64_t *seg_offsets, uint32_t num_segs, uint64_t n_total,
+                    void *keys_out, uint32_t *payload_out, uint32_t *perm_out, void *workspace,
+                    size_t workspace_bytes, void *stream);
+
+/* Status word of a workspace after the work enqueued on `stream` has
+ * completed (synchronises `stream`).  Returns RSORT_OK or the device-detected
+ * error. */
+int rsort_workspace_status(const void *workspace, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Diagnostics of the last call that used `workspace` (synchronises stream).
+ * Level 0 of segment 0 is recorded: its splitters in sorted order (the
+ * sample elements chosen, as (ord key, position) pairs; keys are u64 holding
+ * the ordinal key -- for f32 keys the totalOrder bits) and the sizes of its
+ * buckets.  Host output arrays:
+ *   spl_keys[255], spl_pos[255], bucket_sizes[256]; *num_buckets receives the
+ *   bucket count k (0 if no split happened), *levels the number of levels
+ *   enqueued, level_max[8] the largest bucket produced per level and
+ *   level_buckets[8] the number of non-empty buckets per level, *oversize the
+ *   number of final buckets that needed the fallback sort.
+ * ---------------------------------------------------------------------- */
+int rsort_stats(const void *workspace, void *stream, uint64_t *spl_keys, uint32_t *spl_pos,
+                uint32_t *bucket_sizes, uint32_t *num_buckets, uint32_t *levels,
+                uint32_t *level_max, uint32_t *level_buckets, uint32_t *oversize);
+
+/* ------------------------------------------------------------------------
+ * Tuning.  Fields set to 0 keep their current value.  Applies to calls made
+ * after it returns (process-wide, not thread-safe against concurrent calls).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  uint32_t oversample;   /* samples per bucket a (sample size a * k) */
+  uint32_t target;       /* bucket size a level aims for */
+  uint32_t cap;          /* largest bucket sorted in LDS; larger ones are split */
+  uint32_t max_levels;   /* upper bound on sample-sort levels */
+  uint32_t rfis_max;     /* segments <= rfis_max use RFIS (0 disables: set 1) */
+  uint32_t rquick_max;   /* segments <= rquick_max (and > rfis_max) use RQuick */
+  uint64_t seed;         /* seed of the sample positions and coin flips */
+  uint32_t tile_log2;    /* log2 of elements per count/scatter tile (12 or 13) */
+  uint32_t force_fallback; /* debug: 1 = every final bucket > 64 takes the
+                              global-memory fallback sort, 2 = off (0 keeps) */
+} rsort_tuning;
+
+int rsort_get_tuning(rsort_tuning *out);
+int rsort_set_tuning(const rsort_tuning *in);
+
+/* ------------------------------------------------------------------------
+ * Sort server (continuous batching).  Requests are admitted while the sum of
+ * their footprints (input + output + workspace bytes) fits hbm_budget_bytes
+ * and fewer than max_inflight are on the device; admitted requests run on a
+ * pool of HIP streams so their work overlaps on the device.  Small requests
+ * of the same key type admitted together are sorted by one segmented launch.
+ *
+ * Request buffers are device pointers owned by the caller and must stay
+ * valid until rsort_poll returns something other than RSORT_PENDING.  The
+ * server owns its workspace memory (allocated once per worker slot and
+ * charged to the budget).
+ * ---------------------------------------------------------------------- */
+typedef struct rsort_server rsort_server;
+
+typedef struct {
+  rsort_key_t kt;
+  const void *keys_in;
+  uint64_t n;
+  void *keys_out;
+  uint32_t *perm_out; /* may be NULL */
+} rsort_request;
+
+typedef struct {
+  int status;         /* RSORT_OK, RSORT_PENDING or an error */
+  uint64_t t_submit_ns; /* CLOCK_MONOTONIC timestamps */
+  uint64_t t_start_ns;  /* admitted and enqueued */
+  uint64_t t_done_ns;   /* completion observed by the server */
+  uint32_t batch_size;  /* requests sorted in the same launch */
+} rsort_result;
+
+/* device: HIP device ordinal.  max_inflight: concurrent requests (>= 1). */
+int rsort_server_create(int device, uint64_t hbm_budget_bytes, uint32_t max_inflight,
+                        rsort_server **out);
+/* Waits for every admitted request, then frees server memory. */
+int rsort_server_destroy(rsort_server *s);
+/* Non-blocking.  RSORT_ENOMEM if the request alone exceeds the budget,
+ * RSORT_EINVAL for bad fields.  *ticket_out receives a unique ticket. */
+int rsort_submit(rsort_server *s, const rsort_request *r, uint64_t *ticket_out);
+/* RSORT_PENDING while queued or running; otherwise the request's final
+ * status, with timestamps in *out (may be NULL).  A finished ticket stays
+ * queryable until rsort_release. RSORT_ENOTFOUND for unknown tickets. */
+int rsort_poll(rsort_server *s, uint64_t ticket, rsort_result *out);
+/* Blocks until the ticket finishes (or timeout_ms elapses: RSORT_PENDING). */
+int rsort_wait(rsort_server *s, uint64_t ticket, uint32_t timeout_ms, rsort_result *out);
+/* Forget a finished ticket. */
+int rsort_release(rsort_server *s, uint64_t ticket);
+/* Counters: requests queued, running, finished; bytes in use. */
+int rsort_server_counters(rsort_server *s, uint64_t *queued, uint64_t *running,
+                          uint64_t *finished, uint64_t *bytes_in_use);
+
+/* ------------------------------------------------------------------------
+ * Binary-tree approximate median (paper Section 3.2), computed on the device
+ * for num_problems independent problems of p = 2^log2_p leaves each.
+ *   vals      device u64 values of all problems back to back (unique within a
+ *             problem); problem q's leaf l holds
+ *             vals[q*per_problem + leaf_off[q*(p+1) + l] .. + leaf_off[q*(p+1) + l + 1]).
+ *             A leaf holds at most 64 values, not necessarily sorted.
+ *   leaf_off  device u64 [num_problems * (p + 1)], nondecreasing per problem.
+ *   coins     device u8 [num_problems * (p + 1)]: p leaf coins (used by leaves
+ *             with an odd count: 0 = lower middle, 1 = upper middle), then the
+ *             root coin (0 = element k/2, 1 = element k/2 + 1 of the root window).
+ *   k         even window size, 2 <= k <= 32.
+ *   out       device u64 [2 * num_problems]: {value, side} per problem, side
+ *             = 0 for a real value, 1 for the below-all sentinel, 2 for the
+ *             above-all sentinel (value 0 then).
+ * Leaves forward the k values around their median, padded with the two
+ * sentinels; inner nodes merge their children's windows and forward the
+ * middle k; the root returns one of its two middle values.
+ * workspace: rsort_median_tree_workspace(log2_p, k, num_problems) bytes.
+ * Errors: RSORT_EINVAL (k odd / out of range, log2_p > 24, NULL pointers),
+ * RSORT_ENOMEM (workspace too small), RSORT_EDEVICE.
+ * ---------------------------------------------------------------------- */
+size_t rsort_median_tree_workspace(uint32_t log2_p, uint32_t k, uint32_t num_problems);
+int rsort_median_tree(const uint64_t *vals, uint64_t per_problem, const uint64_t *leaf_off,
+                      uint32_t log2_p, uint32_t k, const uint8_t *coins, uint32_t num_problems,
+                      uint64_t *out, void *workspace, size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSORT_H */

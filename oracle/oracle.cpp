@@ -151,6 +151,20 @@ int oracle_sort_mt(int kt, const void *keys, uint64_t n, const uint32_t *payload
   return 0;
 }
 
+/* Rank of element i by its definition, in O(n):
+ * #{j : ord(x_j) < ord(x_i)} + #{j < i : ord(x_j) = ord(x_i)}.
+ * Returns UINT64_MAX on bad arguments. */
+uint64_t oracle_rank(int kt, const void *keys, uint64_t n, uint64_t i) {
+  if (bad_kt(kt) || i >= n) return ~0ull;
+  const uint64_t xi = key_ord(kt, keys, i);
+  uint64_t r = 0;
+  for (uint64_t j = 0; j < n; j++) {
+    const uint64_t xj = key_ord(kt, keys, j);
+    r += (xj < xi) || (xj == xi && j < i);
+  }
+  return r;
+}
+
 /* Segmented sort: segment s is [offsets[s], offsets[s+1]); positions are
  * segment-local.  Offsets must be nondecreasing.  Returns 0 or -1. */
 int oracle_segmented(int kt, const void *keys, const uint32_t *payload, const uint64_t *offsets,

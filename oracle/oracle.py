@@ -53,6 +53,8 @@ def lib():
         L.oracle_segmented.argtypes = [i32, vp, vp, vp, u64, vp, vp, vp]
         L.oracle_classify.restype = i32
         L.oracle_classify.argtypes = [i32, vp, vp, u64, vp, vp, u64, vp]
+        L.oracle_rank.restype = u64
+        L.oracle_rank.argtypes = [i32, vp, u64, u64]
         L.oracle_median_tree.restype = i32
         L.oracle_median_tree.argtypes = [vp, vp, u32, u32, vp, vp, vp]
         _lib = L
@@ -87,6 +89,12 @@ def sort(keys: np.ndarray, payload: np.ndarray | None = None, threads: int = 1):
     if rc != 0:
         raise ValueError("oracle_sort rejected its arguments")
     return ko, po, plo
+
+
+def rank(keys: np.ndarray, i: int) -> int:
+    """Rank of element i (its output position) straight from the definition, O(n)."""
+    keys = np.ascontiguousarray(keys)
+    return int(lib().oracle_rank(kt_of(keys), _ptr(keys), keys.size, i))
 
 
 def segmented(keys: np.ndarray, offsets: np.ndarray, payload: np.ndarray | None = None):

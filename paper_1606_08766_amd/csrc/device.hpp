@@ -1,0 +1,244 @@
+// Device primitives shared by the rsort kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rs {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Keys.  Every kernel works on "ordinal" keys: unsigned integers whose
+// unsigned order is the sort order.  u32/u64 keys are their own ordinals; an
+// f32 key maps to its IEEE 754 totalOrder ordinal (negative patterns are
+// bit-inverted, non-negative ones get the sign bit set), which is a bijection,
+// so the original bits are restored exactly on output.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t f32_ord(uint32_t u) {
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ uint32_t f32_unord(uint32_t o) {
+  return (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+}
+
+template <typename K>
+struct KMax;
+template <>
+struct KMax<uint32_t> {
+  static constexpr uint32_t v = 0xFFFFFFFFu;
+};
+template <>
+struct KMax<uint64_t> {
+  static constexpr uint64_t v = ~0ull;
+};
+
+// Padding element: above every real (key, position) pair because real
+// positions are < 2^32 - 1.
+constexpr uint32_t kPadIdx = 0xFFFFFFFFu;
+
+template <typename K>
+__device__ __forceinline__ bool pair_less(K ka, uint32_t ia, K kb, uint32_t ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
+
+template <typename K, bool F32>
+__device__ __forceinline__ K load_ord(const K* p, uint64_t i) {
+  K v = p[i];
+  if constexpr (F32) return (K)f32_ord((uint32_t)v);
+  return v;
+}
+template <typename K, bool F32>
+__device__ __forceinline__ K to_output(K o) {
+  if constexpr (F32) return (K)f32_unord((uint32_t)o);
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// Counter-based random numbers for sample positions and coin flips:
+// SplitMix64's output function applied to a counter (Steele, Lea, Flood 2014).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t rand_at(uint64_t seed, uint64_t stream, uint64_t i) {
+  return mix64(seed + mix64(stream + 0x632BE59BD9B4E019ull) + (i + 1) * 0x9E3779B97F4A7C15ull);
+}
+
+// ---------------------------------------------------------------------------
+// Wave / block scans.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Inclusive scan across the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint32_t o = __shfl_up(v, d, kWave);
+    if (lane >= (uint32_t)d) v += o;
+  }
+  return v;
+}
+
+// Exclusive block scan of one value per thread.  `tmp` holds >= THREADS/64 + 1
+// words of LDS.  Returns the exclusive prefix; *total receives the block sum.
+template <int THREADS>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
+  constexpr int NW = THREADS / kWave;
+  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  uint32_t inc = wave_incl_scan(v);
+  if (lane == kWave - 1) tmp[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < NW; i++) {
+      uint32_t t = tmp[i];
+      tmp[i] = s;
+      s += t;
+    }
+    tmp[NW] = s;
+  }
+  __syncthreads();
+  uint32_t r = tmp[w] + inc - v;
+  if (total) *total = tmp[NW];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Register sorting network (bitonic) on ITEMS (power of two) pairs, ascending.
+// ---------------------------------------------------------------------------
+template <typename K, int ITEMS>
+__device__ __forceinline__ void reg_sort(K (&k)[ITEMS], uint32_t (&v)[ITEMS]) {
+#pragma unroll
+  for (int size = 2; size <= ITEMS; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool asc = (i & size) == 0;
+          const bool sw = asc ? pair_less(k[j], v[j], k[i], v[i]) : pair_less(k[i], v[i], k[j], v[j]);
+          K tk = sw ? k[j] : k[i];
+          uint32_t tv = sw ? v[j] : v[i];
+          k[j] = sw ? k[i] : k[j];
+          v[j] = sw ? v[i] : v[j];
+          k[i] = tk;
+          v[i] = tv;
+        }
+      }
+    }
+  }
+}
+
+// Same network carrying a third value.
+template <typename K, int ITEMS>
+__device__ __forceinline__ void reg_sort3(K (&k)[ITEMS], uint32_t (&v)[ITEMS], uint32_t (&p)[ITEMS]) {
+#pragma unroll
+  for (int size = 2; size <= ITEMS; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool asc = (i & size) == 0;
+          const bool sw = asc ? pair_less(k[j], v[j], k[i], v[i]) : pair_less(k[i], v[i], k[j], v[j]);
+          K tk = sw ? k[j] : k[i];
+          uint32_t tv = sw ? v[j] : v[i];
+          uint32_t tp = sw ? p[j] : p[i];
+          k[j] = sw ? k[i] : k[j];
+          v[j] = sw ? v[i] : v[j];
+          p[j] = sw ? p[i] : p[j];
+          k[i] = tk;
+          v[i] = tv;
+          p[i] = tp;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block merge sort of N = THREADS * ITEMS pairs (N need not be a power of two;
+// ITEMS must be).
+// On entry thread t holds logical elements t*ITEMS .. t*ITEMS+ITEMS-1 in
+// k/v (and p if CARRY); on exit it holds sorted ranks t*ITEMS .. likewise.
+// sk/sv/sp: LDS arrays of N entries.  Pairs must be distinct except for
+// padding copies.  Each round merges adjacent sorted runs: every thread finds
+// where its ITEMS outputs start with a merge-path binary search and merges
+// them serially from LDS.  Ties (padding only) prefer the left run in both
+// the search and the serial merge, so the two always agree.
+// ---------------------------------------------------------------------------
+// With GROUP < THREADS, runs never cross aligned groups of GROUP threads: each
+// group of GROUP * ITEMS elements is sorted independently (GROUP must then be
+// a power of two dividing THREADS).
+template <typename K, int THREADS, int ITEMS, bool CARRY, int GROUP = THREADS>
+__device__ __forceinline__ void block_merge_sort(K (&k)[ITEMS], uint32_t (&v)[ITEMS],
+                                                 uint32_t (&p)[ITEMS], K* sk, uint32_t* sv,
+                                                 uint32_t* sp) {
+  constexpr int N = THREADS * ITEMS;
+  if constexpr (CARRY)
+    reg_sort3<K, ITEMS>(k, v, p);
+  else
+    reg_sort<K, ITEMS>(k, v);
+  const int t = threadIdx.x;
+#pragma unroll 1
+  for (int run = ITEMS; run < GROUP * ITEMS; run <<= 1) {
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      sk[t * ITEMS + i] = k[i];
+      sv[t * ITEMS + i] = v[i];
+      if constexpr (CARRY) sp[t * ITEMS + i] = p[i];
+    }
+    __syncthreads();
+    const int first = (t * ITEMS) & ~(2 * run - 1);
+    const int a0 = first, b0 = first + run;
+    const int alen = (N - a0) < run ? (N - a0) : run;
+    const int blen = (N - b0) <= 0 ? 0 : ((N - b0) < run ? (N - b0) : run);
+    const int d = t * ITEMS - first;
+    int lo = d > blen ? d - blen : 0;
+    int hi = d < alen ? d : alen;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      const int bj = b0 + d - 1 - mid;
+      if (pair_less(sk[bj], sv[bj], sk[a0 + mid], sv[a0 + mid]))
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    int ai = lo, bi = d - lo;
+    K ka = ai < alen ? sk[a0 + ai] : K(0);
+    uint32_t va = ai < alen ? sv[a0 + ai] : 0u;
+    K kb = bi < blen ? sk[b0 + bi] : K(0);
+    uint32_t vb = bi < blen ? sv[b0 + bi] : 0u;
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const bool takeA = ai < alen && (bi >= blen || !pair_less(kb, vb, ka, va));
+      k[i] = takeA ? ka : kb;
+      v[i] = takeA ? va : vb;
+      if constexpr (CARRY) p[i] = takeA ? sp[a0 + ai] : sp[b0 + bi];
+      if (takeA) {
+        ai++;
+        if (ai < alen) {
+          ka = sk[a0 + ai];
+          va = sv[a0 + ai];
+        }
+      } else {
+        bi++;
+        if (bi < blen) {
+          kb = sk[b0 + bi];
+          vb = sv[b0 + bi];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace rs

@@ -1,0 +1,736 @@
+// Multilevel sample sort engine (paper Appendix G: robust multi-level sample
+// sort, RAMS) for one GPU, plus the LDS sort of its final buckets.
+//
+// One level splits every "big" segment (more than `cap` elements) into
+// k = 2^logk buckets:
+//   splitters  draw a*k random sample positions per segment, gather
+//              (key, position) pairs, sort them in LDS and keep every a-th
+//              as a splitter (positions break key ties, Appendix G);
+//   count      classify every element with a branchless descent of the
+//              splitter tree held in LDS (a Super Scalar Sample Sort style
+//              classifier; a key equal to a splitter key is resolved by the
+//              positions) and histogram buckets per tile;
+//   scan       exclusive prefix sum of the [segment][bucket][tile] counts;
+//   scatter    re-classify, rank inside (tile, bucket) with LDS atomics,
+//              stage the tile in LDS grouped by bucket and write contiguous
+//              runs: the paper's all-to-all exchange becomes a scatter
+//              through HBM at prefix-sum offsets.
+// Buckets at most `cap` long become final segments and are sorted, one
+// workgroup each, in LDS; the rest are split again at the next level.
+// Everything is sized on the device: no bucket size returns to the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+
+#include "device.hpp"
+#include "engine.hpp"
+#include "internal.hpp"
+
+namespace rs {
+
+// Size classes of final segments (upper bounds); the last is "oversize".
+__constant__ uint32_t c_class_max[kNumClasses] = {64, 256, 1024, 2048, 4096, 8192, 12288, 0xFFFFFFFFu};
+static const uint32_t h_class_max[kNumClasses] = {64, 256, 1024, 2048, 4096, 8192, 12288, 0xFFFFFFFFu};
+
+__device__ __forceinline__ uint32_t class_of(uint32_t len, uint32_t cap, uint32_t force_fallback) {
+  if (len > cap || (force_fallback && len > 64)) return kNumClasses - 1;
+  uint32_t c = 0;
+  while (len > c_class_max[c]) c++;
+  return c;
+}
+
+__device__ __forceinline__ uint32_t logk_for(uint32_t len, uint32_t target) {
+  uint32_t q = (len + target - 1) / target;  // buckets wanted
+  uint32_t lk = q <= 1 ? 1u : 32u - __clz(q - 1);
+  return lk > (uint32_t)kMaxLogK ? (uint32_t)kMaxLogK : lk;
+}
+
+__device__ __forceinline__ void set_status(Ctl* ctl, int32_t code) { atomicCAS(&ctl->status, 0, code); }
+
+__device__ __forceinline__ void push_final(const Work& w, uint64_t start, uint32_t len, uint32_t src,
+                                           uint32_t cap, uint32_t ff) {
+  const uint32_t c = class_of(len, cap, ff);
+  const uint32_t i = atomicAdd(&w.ctl->class_count[c], 1u);
+  if (i < w.cls_cap[c])
+    w.cls[c][i] = FinalSeg{start, len, src};
+  else
+    set_status(w.ctl, -3);  // capacity bound violated: internal error
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_reset(Ctl* ctl, uint32_t levels) {
+  uint32_t* p = reinterpret_cast<uint32_t*>(ctl);
+  const uint32_t nw = (uint32_t)(offsetof(Ctl, l0_spl_key) / 4);
+  for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) p[i] = (i == 1) ? levels : 0u;
+}
+
+// Route every user segment: split it (big list 0) or sort it directly.
+__global__ void k_init(Work w, const uint64_t* seg_off, uint32_t num_segs, uint64_t n_total, uint32_t cap,
+                       uint32_t target, uint32_t levels, uint32_t ff) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < num_segs; s += stride) {
+    const uint64_t a = seg_off ? seg_off[s] : 0ull;
+    const uint64_t b = seg_off ? seg_off[s + 1] : n_total;
+    if (b < a || b > n_total || (s == 0 && a != 0) || (s + 1 == num_segs && b != n_total) ||
+        b - a >= 0xFFFFFFFFull) {
+      set_status(w.ctl, -1);
+      continue;
+    }
+    const uint32_t len = (uint32_t)(b - a);
+    if (len == 0) continue;
+    if (len > cap && levels > 0) {
+      const uint32_t i = atomicAdd(&w.ctl->big_count[0], 1u);
+      if (i < w.big_max)
+        w.big[0][i] = BigSeg{a, a, len, logk_for(len, target)};
+      else
+        set_status(w.ctl, -3);
+    } else {
+      push_final(w, a, len, 0u, cap, ff);
+    }
+  }
+}
+
+// Per level: tiles and count-matrix bases of the segments to split.
+constexpr int kPlanThreads = 1024;
+__global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev, uint32_t tile) {
+  __shared__ uint32_t tmp[kPlanThreads / kWave + 1];
+  const int cur = lev & 1;
+  const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
+  const BigSeg* B = w.big[cur];
+  uint32_t ct = 0, cc = 0;
+  for (uint32_t base = 0; base < m; base += kPlanThreads) {
+    const uint32_t i = base + threadIdx.x;
+    uint32_t nt = 0, nc = 0;
+    if (i < m) {
+      nt = (B[i].len + tile - 1) / tile;
+      nc = nt << B[i].logk;
+    }
+    uint32_t tt, tc;
+    const uint32_t et = block_excl_scan<kPlanThreads>(nt, tmp, &tt);
+    const uint32_t ec = block_excl_scan<kPlanThreads>(nc, tmp, &tc);
+    if (i < m) {
+      w.tile_base[i] = ct + et;
+      w.count_base[i] = cc + ec;
+    }
+    ct += tt;
+    cc += tc;
+  }
+  if (threadIdx.x == 0) {
+    w.tile_base[m] = ct;
+    w.count_base[m] = cc;
+    w.ctl->total_tiles = ct;
+    w.ctl->total_counts = cc;
+    w.ctl->big_count[cur ^ 1] = 0;
+  }
+}
+
+// Splitter selection: one workgroup per segment.  S = a << logk sample
+// positions drawn uniformly (with replacement) from the segment; the
+// (key, position) pairs are sorted in LDS and every a-th becomes a splitter.
+// The k-1 splitters are stored as an implicit binary search tree: node t at
+// depth d, index q = t - 2^d within its depth, holds splitter number
+// (2q+1) * 2^(logk-1-d) (1-based, in sorted order).
+template <typename K, bool F32, bool SRC_IN, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K* in_keys, int src_buf,
+                                                       uint32_t a, uint64_t seed) {
+  constexpr int N = THREADS * ITEMS;
+  __shared__ K sk[N];
+  __shared__ uint32_t sv[N];
+  const int cur = lev & 1;
+  const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
+  const K* bkey = SRC_IN ? nullptr : (const K*)w.buf_key[src_buf];
+  const uint32_t* bidx = SRC_IN ? nullptr : w.buf_idx[src_buf];
+  K* tkey = (K*)w.tree_key;
+  for (uint32_t s = blockIdx.x; s < m; s += gridDim.x) {
+    const BigSeg bs = w.big[cur][s];
+    const uint32_t S = a << bs.logk;  // <= N by construction
+    K k[ITEMS];
+    uint32_t v[ITEMS], p[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const uint32_t j = threadIdx.x * ITEMS + i;
+      if (j < S) {
+        const uint64_t r = rand_at(seed, ((uint64_t)lev << 40) ^ bs.start, j);
+        const uint64_t pos = bs.start + (((r >> 32) * (uint64_t)bs.len) >> 32);
+        if constexpr (SRC_IN) {
+          k[i] = load_ord<K, F32>(in_keys, pos);
+          v[i] = (uint32_t)(pos - bs.ubase);
+        } else {
+          k[i] = bkey[pos];
+          v[i] = bidx[pos];
+        }
+      } else {
+        k[i] = KMax<K>::v;
+        v[i] = kPadIdx;
+      }
+      p[i] = 0;
+    }
+    block_merge_sort<K, THREADS, ITEMS, false>(k, v, p, sk, sv, nullptr);
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      sk[threadIdx.x * ITEMS + i] = k[i];
+      sv[threadIdx.x * ITEMS + i] = v[i];
+    }
+    __syncthreads();
+    const uint32_t kk = 1u << bs.logk;
+    for (uint32_t node = threadIdx.x + 1; node < kk; node += THREADS) {
+      const uint32_t d = 31u - __clz(node);
+      const uint32_t q = node - (1u << d);
+      const uint32_t j = (2u * q + 1u) << (bs.logk - 1u - d);
+      const uint32_t r = j * a - 1u;
+      tkey[(uint64_t)s * kMaxK + node] = sk[r];
+      w.tree_idx[(uint64_t)s * kMaxK + node] = sv[r];
+    }
+    if (lev == 0 && s == 0) {
+      for (uint32_t j = threadIdx.x + 1; j < kk; j += THREADS) {
+        w.ctl->l0_spl_key[j - 1] = (uint64_t)sk[j * a - 1u];
+        w.ctl->l0_spl_pos[j - 1] = sv[j * a - 1u];
+      }
+      if (threadIdx.x == 0) w.ctl->l0_k = kk;
+    }
+    __syncthreads();
+  }
+}
+
+// Classification with positional tie-break: bucket = number of splitters
+// strictly below (key, idx).
+template <typename K>
+__device__ __forceinline__ uint32_t classify(const K* tk, const uint32_t* ti, uint32_t logk, K key,
+                                             uint32_t idx) {
+  uint32_t j = 1;
+  for (uint32_t l = 0; l < logk; l++) {
+    const K t = tk[j];
+    const uint32_t u = ti[j];
+    j = 2u * j + ((key > t) | ((key == t) & (idx > u)) ? 1u : 0u);
+  }
+  return j - (1u << logk);
+}
+
+__device__ __forceinline__ uint32_t find_seg(const uint32_t* base, uint32_t m, uint32_t tile) {
+  uint32_t lo = 0, hi = m;  // base[0] = 0 <= tile < base[m]
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (base[mid] <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename K, bool F32, bool SRC_IN, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_keys, int src_buf) {
+  constexpr uint32_t TILE = THREADS * ITEMS;
+  __shared__ K tk[kMaxK];
+  __shared__ uint32_t ti[kMaxK];
+  __shared__ uint32_t hist[kMaxK];
+  __shared__ uint32_t sh_s;
+  const int cur = lev & 1;
+  const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
+  const uint32_t T = w.ctl->total_tiles;
+  const K* bkey = SRC_IN ? nullptr : (const K*)w.buf_key[src_buf];
+  const uint32_t* bidx = SRC_IN ? nullptr : w.buf_idx[src_buf];
+  const K* tkey = (const K*)w.tree_key;
+  for (uint32_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
+    if (threadIdx.x == 0) sh_s = find_seg(w.tile_base, m, tile);
+    __syncthreads();
+    const uint32_t s = sh_s;
+    const BigSeg bs = w.big[cur][s];
+    const uint32_t tl = tile - w.tile_base[s];
+    const uint32_t nt = w.tile_base[s + 1] - w.tile_base[s];
+    const uint32_t kk = 1u << bs.logk;
+    for (uint32_t i = threadIdx.x; i < kk; i += THREADS) {
+      hist[i] = 0;
+      if (i) {
+        tk[i] = tkey[(uint64_t)s * kMaxK + i];
+        ti[i] = w.tree_idx[(uint64_t)s * kMaxK + i];
+      }
+    }
+    __syncthreads();
+    const uint64_t base = bs.start + (uint64_t)tl * TILE;
+    const uint32_t cnt = min(TILE, bs.len - tl * TILE);
+#pragma unroll 4
+    for (int i = 0; i < ITEMS; i++) {
+      const uint32_t j = i * THREADS + threadIdx.x;
+      if (j < cnt) {
+        K key;
+        uint32_t idx;
+        if constexpr (SRC_IN) {
+          key = load_ord<K, F32>(in_keys, base + j);
+          idx = (uint32_t)(base + j - bs.ubase);
+        } else {
+          key = bkey[base + j];
+          idx = bidx[base + j];
+        }
+        atomicAdd(&hist[classify<K>(tk, ti, bs.logk, key, idx)], 1u);
+      }
+    }
+    __syncthreads();
+    const uint32_t cb = w.count_base[s];
+    for (uint32_t b = threadIdx.x; b < kk; b += THREADS) w.counts[cb + b * nt + tl] = hist[b];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of counts[0 .. total_counts) into offsets (reduce-then-scan).
+constexpr int kScanThreads = 256, kScanItems = 16, kScanChunk = kScanThreads * kScanItems;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(Work w) {
+  __shared__ uint32_t tmp[kScanThreads / kWave + 1];
+  const uint32_t M = w.ctl->total_counts;
+  const uint32_t nb = (M + kScanChunk - 1) / kScanChunk;
+  for (uint32_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
+    uint32_t s = 0;
+    const uint64_t base = (uint64_t)blk * kScanChunk;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+      const uint64_t j = base + i * kScanThreads + threadIdx.x;
+      if (j < M) s += w.counts[j];
+    }
+    uint32_t tot;
+    block_excl_scan<kScanThreads>(s, tmp, &tot);
+    if (threadIdx.x == 0) w.partials[blk] = tot;
+  }
+}
+
+constexpr int kScanTopThreads = 1024;
+__global__ __launch_bounds__(kScanTopThreads) void k_scan_partials(Work w) {
+  __shared__ uint32_t tmp[kScanTopThreads / kWave + 1];
+  const uint32_t M = w.ctl->total_counts;
+  const uint32_t nb = (M + kScanChunk - 1) / kScanChunk;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < nb; base += kScanTopThreads) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t v = i < nb ? w.partials[i] : 0u;
+    uint32_t tot;
+    const uint32_t e = block_excl_scan<kScanTopThreads>(v, tmp, &tot);
+    if (i < nb) w.partials[i] = carry + e;
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(Work w) {
+  __shared__ uint32_t tmp[kScanThreads / kWave + 1];
+  const uint32_t M = w.ctl->total_counts;
+  const uint32_t nb = (M + kScanChunk - 1) / kScanChunk;
+  for (uint32_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
+    const uint64_t base = (uint64_t)blk * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+      v[i] = (base + i < M) ? w.counts[base + i] : 0u;
+      s += v[i];
+    }
+    uint32_t e = block_excl_scan<kScanThreads>(s, tmp, nullptr) + w.partials[blk];
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+      if (base + i < M) w.offsets[base + i] = e;
+      e += v[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Scatter: classify, rank inside (tile, bucket), stage by bucket in LDS and
+// write each bucket's run contiguously to the destination buffer.
+template <typename K, bool F32, bool SRC_IN, bool PAY, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* in_keys, const uint32_t* in_pay,
+                                                     int src_buf, int dst_buf) {
+  constexpr uint32_t TILE = THREADS * ITEMS;
+  __shared__ K tk[kMaxK];
+  __shared__ uint32_t ti[kMaxK];
+  __shared__ uint32_t hist[kMaxK];
+  __shared__ uint64_t gdelta[kMaxK];
+  __shared__ uint32_t tmp[THREADS / kWave + 1];
+  __shared__ uint32_t sh_s;
+  __shared__ K stage[TILE];
+  __shared__ uint8_t stage_b[TILE];
+  uint32_t* stage32 = reinterpret_cast<uint32_t*>(stage);
+
+  const int cur = lev & 1;
+  const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
+  const uint32_t T = w.ctl->total_tiles;
+  const K* bkey = SRC_IN ? nullptr : (const K*)w.buf_key[src_buf];
+  const uint32_t* bidx = SRC_IN ? nullptr : w.buf_idx[src_buf];
+  const uint32_t* bpay = SRC_IN ? in_pay : w.buf_pay[src_buf];
+  K* dkey = (K*)w.buf_key[dst_buf];
+  uint32_t* didx = w.buf_idx[dst_buf];
+  uint32_t* dpay = w.buf_pay[dst_buf];
+  const K* tkey = (const K*)w.tree_key;
+
+  for (uint32_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
+    if (threadIdx.x == 0) sh_s = find_seg(w.tile_base, m, tile);
+    __syncthreads();
+    const uint32_t s = sh_s;
+    const BigSeg bs = w.big[cur][s];
+    const uint32_t tl = tile - w.tile_base[s];
+    const uint32_t nt = w.tile_base[s + 1] - w.tile_base[s];
+    const uint32_t kk = 1u << bs.logk;
+    const uint32_t cb = w.count_base[s];
+    const uint32_t seg0 = w.offsets[cb];
+    for (uint32_t i = threadIdx.x; i < kk; i += THREADS) {
+      hist[i] = 0;
+      if (i) {
+        tk[i] = tkey[(uint64_t)s * kMaxK + i];
+        ti[i] = w.tree_idx[(uint64_t)s * kMaxK + i];
+      }
+      gdelta[i] = bs.start + (uint64_t)(w.offsets[cb + i * nt + tl] - seg0);
+    }
+    __syncthreads();
+    const uint64_t base = bs.start + (uint64_t)tl * TILE;
+    const uint32_t cnt = min(TILE, bs.len - tl * TILE);
+    K key[ITEMS];
+    uint32_t idx[ITEMS], pay[ITEMS], pos[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const uint32_t j = i * THREADS + threadIdx.x;
+      pos[i] = 0xFFFFFFFFu;
+      if (j < cnt) {
+        if constexpr (SRC_IN) {
+          key[i] = load_ord<K, F32>(in_keys, base + j);
+          idx[i] = (uint32_t)(base + j - bs.ubase);
+        } else {
+          key[i] = bkey[base + j];
+          idx[i] = bidx[base + j];
+        }
+        if constexpr (PAY) pay[i] = bpay[base + j];
+        const uint32_t b = classify<K>(tk, ti, bs.logk, key[i], idx[i]);
+        const uint32_t r = atomicAdd(&hist[b], 1u);
+        pos[i] = (b << 24) | r;  // r < TILE <= 2^24
+      }
+    }
+    __syncthreads();
+    // exclusive scan of the tile histogram -> tile-local bucket starts
+    {
+      static_assert(THREADS >= kMaxK, "one histogram bin per thread");
+      const uint32_t hv = threadIdx.x < kk ? hist[threadIdx.x] : 0u;
+      const uint32_t e = block_excl_scan<THREADS>(hv, tmp, nullptr);
+      if (threadIdx.x < kk) hist[threadIdx.x] = e;
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < kk; b += THREADS) gdelta[b] -= hist[b];
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      if (pos[i] != 0xFFFFFFFFu) {
+        const uint32_t b = pos[i] >> 24;
+        const uint32_t p = hist[b] + (pos[i] & 0xFFFFFFu);
+        pos[i] = p;
+        stage[p] = key[i];
+        stage_b[p] = (uint8_t)b;
+      }
+    }
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) dkey[gdelta[stage_b[p]] + p] = stage[p];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++)
+      if (pos[i] != 0xFFFFFFFFu) stage32[pos[i]] = idx[i];
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) didx[gdelta[stage_b[p]] + p] = stage32[p];
+    if constexpr (PAY) {
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++)
+        if (pos[i] != 0xFFFFFFFFu) stage32[pos[i]] = pay[i];
+      __syncthreads();
+      for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) dpay[gdelta[stage_b[p]] + p] = stage32[p];
+    }
+    __syncthreads();
+  }
+}
+
+// Buckets of the finished level: split again or sort in LDS.
+__global__ void k_level_end(Work w, int lev, uint32_t cap, uint32_t target, int last, uint32_t dst_code,
+                            uint32_t ff) {
+  const int cur = lev & 1;
+  const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
+  const uint64_t total = (uint64_t)m * kMaxK;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+    const uint32_t s = (uint32_t)(g / kMaxK), b = (uint32_t)(g % kMaxK);
+    const BigSeg bs = w.big[cur][s];
+    const uint32_t kk = 1u << bs.logk;
+    if (b >= kk) continue;
+    const uint32_t nt = w.tile_base[s + 1] - w.tile_base[s];
+    const uint32_t cb = w.count_base[s];
+    const uint32_t seg0 = w.offsets[cb];
+    const uint32_t lo = w.offsets[cb + b * nt] - seg0;
+    const uint32_t hi = (b + 1 < kk) ? w.offsets[cb + (b + 1) * nt] - seg0 : bs.len;
+    const uint32_t len = hi - lo;
+    if (lev == 0 && s == 0) w.ctl->l0_bucket[b] = len;
+    if (lev < kMaxLevels) {
+      atomicMax(&w.ctl->level_max[lev], len);
+      if (len) atomicAdd(&w.ctl->level_buckets[lev], 1u);
+    }
+    if (len == 0) continue;
+    const uint64_t start = bs.start + lo;
+    if (len > cap && !last) {
+      const uint32_t i = atomicAdd(&w.ctl->big_count[cur ^ 1], 1u);
+      if (i < w.big_max)
+        w.big[cur ^ 1][i] = BigSeg{start, bs.ubase, len, logk_for(len, target)};
+      else
+        set_status(w.ctl, -3);
+    } else {
+      push_final(w, start, len, dst_code, cap, ff);
+    }
+  }
+}
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+static Tuning g_tuning;
+
+Tuning& tuning() { return g_tuning; }
+
+static inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+uint32_t plan_levels(uint64_t n, const Tuning& t, uint32_t cap) {
+  if (n <= cap) return 0;
+  uint32_t L = 0;
+  uint64_t reach = std::max<uint32_t>(64u, std::min<uint32_t>(t.target, cap / 3));
+  while (reach < n) {
+    reach <<= kMaxLogK;
+    L++;
+  }
+  L = std::max<uint32_t>(L, 1);
+  return std::min<uint32_t>(L, std::min<uint32_t>(t.max_levels, kMaxLevels));
+}
+
+uint32_t effective_cap(const Tuning& t, bool pay) {
+  uint32_t cap = std::min<uint32_t>(t.cap, pay ? 8192u : 12288u);
+  return std::max<uint32_t>(cap, 64u);
+}
+
+// Workspace layout: returns total bytes; fills w (pointers relative to base).
+size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, char* base, Work* w,
+              uint32_t* levels_out) {
+  const uint64_t ks = kt == 1 ? 8 : 4;
+  const uint32_t cap = effective_cap(t, pay);
+  const uint32_t levels = plan_levels(n, t, cap);
+  const uint32_t tile = 1u << t.tile_log2;
+  const uint64_t big_max = levels ? n / (cap + 1) + 1 : 0;
+  const uint64_t tiles_max = levels ? n / tile + big_max + 1 : 0;
+  const uint64_t count_max = tiles_max * kMaxK;
+  const uint64_t scan_blocks = count_max / kScanChunk + 2;
+  const uint64_t final_max = (uint64_t)num_segs + (uint64_t)levels * kMaxK * big_max + 1;
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  const uint64_t o_ctl = take(sizeof(Ctl));
+  const uint64_t o_big0 = take(big_max * sizeof(BigSeg));
+  const uint64_t o_big1 = take(big_max * sizeof(BigSeg));
+  const uint64_t o_tb = take((big_max + 1) * 4);
+  const uint64_t o_cb = take((big_max + 1) * 4);
+  const uint64_t o_tk = take(big_max * kMaxK * ks);
+  const uint64_t o_ti = take(big_max * kMaxK * 4);
+  const uint64_t o_cnt = take(count_max * 4);
+  const uint64_t o_off = take(count_max * 4);
+  const uint64_t o_par = take(scan_blocks * 4);
+  uint64_t o_cls[kNumClasses], cls_cap[kNumClasses];
+  for (int c = 0; c < kNumClasses; c++) {
+    const uint64_t lo = c == 0 ? 0 : h_class_max[c - 1];
+    uint64_t bound = n / (lo + 1) + 1;
+    if (c == kNumClasses - 1) bound = n / (std::min<uint64_t>(cap, 64) + 1) + 1;
+    cls_cap[c] = std::min<uint64_t>(final_max, bound);
+    o_cls[c] = take(cls_cap[c] * sizeof(FinalSeg));
+  }
+  const uint64_t nb = (levels || t.force_fallback) ? n : 0;
+  uint64_t o_bk[2], o_bi[2], o_bp[2];
+  for (int b = 0; b < 2; b++) {
+    o_bk[b] = take(nb * ks);
+    o_bi[b] = take(nb * 4);
+    o_bp[b] = take(pay ? nb * 4 : 0);
+  }
+  if (w) {
+    w->ctl = (Ctl*)(base + o_ctl);
+    w->big[0] = (BigSeg*)(base + o_big0);
+    w->big[1] = (BigSeg*)(base + o_big1);
+    w->tile_base = (uint32_t*)(base + o_tb);
+    w->count_base = (uint32_t*)(base + o_cb);
+    w->tree_key = base + o_tk;
+    w->tree_idx = (uint32_t*)(base + o_ti);
+    w->counts = (uint32_t*)(base + o_cnt);
+    w->offsets = (uint32_t*)(base + o_off);
+    w->partials = (uint32_t*)(base + o_par);
+    for (int c = 0; c < kNumClasses; c++) {
+      w->cls[c] = (FinalSeg*)(base + o_cls[c]);
+      w->cls_cap[c] = cls_cap[c];
+    }
+    for (int b = 0; b < 2; b++) {
+      w->buf_key[b] = base + o_bk[b];
+      w->buf_idx[b] = (uint32_t*)(base + o_bi[b]);
+      w->buf_pay[b] = pay ? (uint32_t*)(base + o_bp[b]) : nullptr;
+    }
+    w->big_max = big_max;
+    w->count_max = count_max;
+    w->scan_blocks = scan_blocks;
+    w->n = n;
+  }
+  if (levels_out) *levels_out = levels;
+  return off;
+}
+
+static int g_num_cu = 0;
+uint32_t num_cu_cached();
+static int num_cu() {
+  if (!g_num_cu) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess)
+      g_num_cu = p.multiProcessorCount;
+    else
+      g_num_cu = 256;
+  }
+  return g_num_cu;
+}
+
+uint32_t num_cu_cached() { return (uint32_t)num_cu(); }
+
+static inline uint32_t grid_for(uint64_t work, uint32_t per_cu) {
+  const uint64_t g = std::min<uint64_t>(work, (uint64_t)num_cu() * per_cu);
+  return (uint32_t)std::max<uint64_t>(g, 1);
+}
+
+#define RS_LAUNCH(kern, grid, block, stream, ...)                                      \
+  do {                                                                                 \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (hipStream_t)(stream), __VA_ARGS__); \
+    if (hipPeekAtLastError() != hipSuccess) return -3;                                 \
+  } while (0)
+
+constexpr int kCntThreads = 256;
+constexpr int kSplThreads = 512, kSplItems = 16;  // up to 8192 samples (a = 32, k = 256)
+
+// Algorithm of each size class: RFIS, RQuick or the LDS merge sort.
+template <typename K, bool F32, bool PAY>
+static int launch_class_sort(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
+                             uint32_t* pay_out, uint64_t cap_c, hipStream_t st, const Tuning& t) {
+  if (h_class_max[c] <= t.rfis_max) return launch_rfis_class<K, F32, PAY>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, st);
+  if (h_class_max[c] <= t.rquick_max)
+    return launch_rquick_class<K, F32, PAY>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, st);
+  return launch_merge_class<K, F32, PAY>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, st);
+}
+
+template <typename K, bool F32, bool PAY>
+static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint64_t* seg_off, uint32_t num_segs,
+                         uint64_t n, void* keys_out, uint32_t* perm_out, uint32_t* pay_out, void* ws,
+                         size_t ws_bytes, hipStream_t st) {
+  const Tuning t = g_tuning;
+  Work w;
+  uint32_t levels = 0;
+  const size_t need = layout(F32 ? 2 : (sizeof(K) == 8 ? 1 : 0), n, num_segs, PAY, t, (char*)ws, &w, &levels);
+  if (ws_bytes < need) return -2;
+  const uint32_t cap = effective_cap(t, PAY);
+  const uint32_t a = std::min<uint32_t>(std::max<uint32_t>(t.oversample, 1), kMaxOversample);
+  const uint32_t ff = t.force_fallback;
+  const uint32_t target = std::max<uint32_t>(64u, std::min<uint32_t>(t.target, cap / 3));
+  const K* kin = (const K*)keys_in;
+  K* kout = (K*)keys_out;
+
+  RS_LAUNCH(k_reset, 1, 256, st, w.ctl, levels);
+  RS_LAUNCH(k_init, grid_for((num_segs + 255) / 256, 4), 256, st, w, seg_off, num_segs, n, cap, target, levels, ff);
+
+  const uint32_t tile_log2 = t.tile_log2 == 13 ? 13 : 12;
+  const uint32_t tile = 1u << tile_log2;
+  const uint64_t tiles_max = n / tile + w.big_max + 1;
+  for (uint32_t lev = 0; lev < levels; lev++) {
+    const int dst = lev & 1;
+    const int src = (lev + 1) & 1;  // buffer written by the previous level
+    const bool last = lev + 1 == levels;
+    RS_LAUNCH(k_plan, 1, kPlanThreads, st, w, (int)lev, tile);
+    const uint32_t gs = grid_for(w.big_max, 4);
+    if (lev == 0) {
+      RS_LAUNCH((k_splitters<K, F32, true, kSplThreads, kSplItems>), gs, kSplThreads, st, w, (int)lev, kin, src, a, t.seed);
+    } else {
+      RS_LAUNCH((k_splitters<K, false, false, kSplThreads, kSplItems>), gs, kSplThreads, st, w, (int)lev, kin, src, a,
+                t.seed);
+    }
+    const uint32_t gt = grid_for(tiles_max, 8);
+    if (tile_log2 == 12) {
+      if (lev == 0)
+        RS_LAUNCH((k_count<K, F32, true, kCntThreads, 16>), gt, kCntThreads, st, w, (int)lev, kin, src);
+      else
+        RS_LAUNCH((k_count<K, false, false, kCntThreads, 16>), gt, kCntThreads, st, w, (int)lev, kin, src);
+    } else {
+      if (lev == 0)
+        RS_LAUNCH((k_count<K, F32, true, kCntThreads, 32>), gt, kCntThreads, st, w, (int)lev, kin, src);
+      else
+        RS_LAUNCH((k_count<K, false, false, kCntThreads, 32>), gt, kCntThreads, st, w, (int)lev, kin, src);
+    }
+    const uint32_t gsc = grid_for(w.count_max / kScanChunk + 1, 8);
+    RS_LAUNCH(k_scan_reduce, gsc, kScanThreads, st, w);
+    RS_LAUNCH(k_scan_partials, 1, kScanTopThreads, st, w);
+    RS_LAUNCH(k_scan_down, gsc, kScanThreads, st, w);
+    if (tile_log2 == 12) {
+      if (lev == 0)
+        RS_LAUNCH((k_scatter<K, F32, true, PAY, kCntThreads, 16>), gt, kCntThreads, st, w, (int)lev, kin, pay_in, src, dst);
+      else
+        RS_LAUNCH((k_scatter<K, false, false, PAY, kCntThreads, 16>), gt, kCntThreads, st, w, (int)lev, kin, pay_in, src,
+                  dst);
+    } else {
+      if (lev == 0)
+        RS_LAUNCH((k_scatter<K, F32, true, PAY, kCntThreads, 32>), gt, kCntThreads, st, w, (int)lev, kin, pay_in, src, dst);
+      else
+        RS_LAUNCH((k_scatter<K, false, false, PAY, kCntThreads, 32>), gt, kCntThreads, st, w, (int)lev, kin, pay_in, src,
+                  dst);
+    }
+    RS_LAUNCH(k_level_end, grid_for((w.big_max * kMaxK + 255) / 256, 4), 256, st, w, (int)lev, cap, target,
+              last ? 1 : 0, (uint32_t)(dst + 1), ff);
+  }
+
+  // final segments by size class (a class can only be non-empty if its lower
+  // bound is below cap)
+  for (int c = 0; c < kNumClasses - 1; c++) {
+    if (c > 0 && h_class_max[c - 1] >= cap) break;
+    const int rc = launch_class_sort<K, F32, PAY>(c, w, kin, pay_in, kout, perm_out, pay_out, w.cls_cap[c], st, t);
+    if (rc) return rc;
+  }
+  {
+    const int rc = launch_oversize<K, F32, PAY>(w, kin, pay_in, kout, perm_out, pay_out, w.cls_cap[kNumClasses - 1], st);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+int enqueue_sort(int kt, const void* keys_in, const uint32_t* pay_in, const uint64_t* seg_off, uint32_t num_segs,
+                 uint64_t n, void* keys_out, uint32_t* perm_out, uint32_t* pay_out, void* ws, size_t ws_bytes,
+                 hipStream_t st) {
+  const bool pay = pay_in && pay_out;
+  if (!pay) {
+    pay_in = nullptr;
+    pay_out = nullptr;
+  }
+  switch (kt) {
+    case 0:
+      return pay ? enqueue_typed<uint32_t, false, true>(keys_in, pay_in, seg_off, num_segs, n, keys_out, perm_out,
+                                                         pay_out, ws, ws_bytes, st)
+                 : enqueue_typed<uint32_t, false, false>(keys_in, pay_in, seg_off, num_segs, n, keys_out, perm_out,
+                                                          pay_out, ws, ws_bytes, st);
+    case 1:
+      return pay ? enqueue_typed<uint64_t, false, true>(keys_in, pay_in, seg_off, num_segs, n, keys_out, perm_out,
+                                                         pay_out, ws, ws_bytes, st)
+                 : enqueue_typed<uint64_t, false, false>(keys_in, pay_in, seg_off, num_segs, n, keys_out, perm_out,
+                                                          pay_out, ws, ws_bytes, st);
+    case 2:
+      return pay ? enqueue_typed<uint32_t, true, true>(keys_in, pay_in, seg_off, num_segs, n, keys_out, perm_out,
+                                                        pay_out, ws, ws_bytes, st)
+                 : enqueue_typed<uint32_t, true, false>(keys_in, pay_in, seg_off, num_segs, n, keys_out, perm_out,
+                                                         pay_out, ws, ws_bytes, st);
+    default:
+      return -1;
+  }
+}
+
+size_t workspace_bytes(int kt, uint64_t n, uint32_t num_segs, bool pay) {
+  return layout(kt, n, num_segs, pay, g_tuning, nullptr, nullptr, nullptr);
+}
+
+}  // namespace rs

@@ -1,0 +1,68 @@
+// Internal layout shared by the host driver and the kernels of the
+// multilevel sample sort engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rs {
+
+constexpr int kMaxLogK = 8;               // at most 256 buckets per level
+constexpr int kMaxK = 1 << kMaxLogK;
+constexpr int kMaxLevels = 8;
+constexpr int kNumClasses = 8;            // final-bucket size classes (see classes[] in engine.hip)
+constexpr uint32_t kMaxOversample = 32;
+
+// A segment that the current level splits.
+struct BigSeg {
+  uint64_t start;  // global position of the first element
+  uint64_t ubase;  // position of the user segment start (input-sourced levels: idx = pos - ubase)
+  uint32_t len;    // number of elements
+  uint32_t logk;   // this segment is split into 1 << logk buckets
+};
+
+// A bucket (or a whole user segment) that is sorted in one workgroup.
+struct FinalSeg {
+  uint64_t start;
+  uint32_t len;
+  uint32_t src;  // 0: caller input (positions implicit), 1: buffer A, 2: buffer B
+};
+
+// Control block at the start of the workspace (all counters device-side).
+struct Ctl {
+  int32_t status;                  // RSORT_OK or a device-detected error
+  uint32_t levels;                 // levels enqueued by the host
+  uint32_t big_count[2];           // ping-pong lists of segments to split
+  uint32_t total_tiles;            // tiles of the current level
+  uint32_t total_counts;           // entries of the current level's count matrix
+  uint32_t class_count[kNumClasses];  // final segments per size class (last = oversize)
+  uint32_t level_max[kMaxLevels];  // largest bucket created per level
+  uint32_t level_buckets[kMaxLevels];
+  // diagnostics of level 0, segment 0
+  uint32_t l0_k;
+  uint32_t pad0;
+  uint64_t l0_spl_key[kMaxK];      // ordinal keys, sorted
+  uint32_t l0_spl_pos[kMaxK];
+  uint32_t l0_bucket[kMaxK];
+};
+
+// Pointers into the workspace for one call.
+struct Work {
+  Ctl* ctl;
+  BigSeg* big[2];
+  uint32_t* tile_base;   // [big_max + 1]
+  uint32_t* count_base;  // [big_max + 1]
+  void* tree_key;        // [big_max * kMaxK] (K), node t of segment s at s*kMaxK + t
+  uint32_t* tree_idx;
+  uint32_t* counts;      // [count_max]
+  uint32_t* offsets;     // [count_max]
+  uint32_t* partials;    // [scan_blocks + 1]
+  FinalSeg* cls[kNumClasses];     // per size class lists
+  uint64_t cls_cap[kNumClasses];
+  void* buf_key[2];      // A, B: [n] keys (ordinal)
+  uint32_t* buf_idx[2];  // [n]
+  uint32_t* buf_pay[2];  // [n] (payload calls only)
+  uint64_t big_max, count_max, scan_blocks, n;
+};
+
+}  // namespace rs

@@ -1,0 +1,58 @@
+// Host-side interfaces between the translation units of librsort.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "engine.hpp"
+
+namespace rs {
+
+struct Tuning {
+  uint32_t oversample = 16;   // samples per bucket
+  uint32_t target = 4096;     // bucket size a level aims for
+  uint32_t cap = 12288;       // largest bucket sorted in LDS
+  uint32_t max_levels = 4;
+  uint32_t rfis_max = 1024;   // classes with upper bound <= rfis_max use RFIS
+  uint32_t rquick_max = 4096; // classes with upper bound <= rquick_max use RQuick
+  uint64_t seed = 0x5EED5EED12345678ull;
+  uint32_t tile_log2 = 12;
+  uint32_t force_fallback = 0;
+};
+
+Tuning& tuning();
+
+// Enqueue a full sort.  seg_off == nullptr means one segment [0, n).
+// Returns 0, -1 (bad argument), -2 (workspace too small), -3 (launch failed).
+int enqueue_sort(int kt, const void* keys_in, const uint32_t* pay_in, const uint64_t* seg_off, uint32_t num_segs,
+                 uint64_t n, void* keys_out, uint32_t* perm_out, uint32_t* pay_out, void* ws, size_t ws_bytes,
+                 hipStream_t st);
+size_t workspace_bytes(int kt, uint64_t n, uint32_t num_segs, bool pay);
+
+// Per-class local sorts (final segments of class c, read from the class list
+// in the workspace).  Merge sort: engine.hip; RFIS / RQuick: small.hip.
+template <typename K, bool F32, bool PAY>
+int launch_merge_class(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
+                       uint32_t* pay_out, uint64_t cap_c, hipStream_t st);
+template <typename K, bool F32, bool PAY>
+int launch_rfis_class(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
+                      uint32_t* pay_out, uint64_t cap_c, hipStream_t st);
+template <typename K, bool F32, bool PAY>
+int launch_rquick_class(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
+                        uint32_t* pay_out, uint64_t cap_c, hipStream_t st);
+
+// Global-memory fallback sort of final segments longer than cap (local.hip).
+template <typename K, bool F32, bool PAY>
+int launch_oversize(const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
+                    uint32_t* pay_out, uint64_t cap_c, hipStream_t st);
+
+// Device binary-tree median (median.hip).
+size_t median_tree_workspace(uint32_t log2_p, uint32_t k, uint32_t num_problems);
+int enqueue_median_tree(const uint64_t* vals, uint64_t per_problem, const uint64_t* leaf_off, uint32_t log2_p,
+                        uint32_t k, const uint8_t* coins, uint32_t num_problems, uint64_t* out, void* ws,
+                        size_t ws_bytes, hipStream_t st);
+
+uint32_t num_cu_cached();
+
+}  // namespace rs

@@ -1,0 +1,263 @@
+// LDS sorts of final segments (one workgroup per segment) and the
+// global-memory fallback for segments longer than the LDS capacity.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device.hpp"
+#include "engine.hpp"
+#include "internal.hpp"
+
+namespace rs {
+
+static inline uint32_t grid_for(uint64_t work, uint32_t per_cu) {
+  const uint64_t g = std::min<uint64_t>(work, (uint64_t)num_cu_cached() * per_cu);
+  return (uint32_t)std::max<uint64_t>(g, 1);
+}
+
+#define RS_LAUNCH(kern, grid, block, stream, ...)                                             \
+  do {                                                                                        \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (hipStream_t)(stream), __VA_ARGS__); \
+    if (hipPeekAtLastError() != hipSuccess) return -3;                                        \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Final segments of one size class: one workgroup each, sorted in LDS.
+template <typename K, bool F32, bool PAY, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K* in_keys, const uint32_t* in_pay,
+                                                        K* keys_out, uint32_t* perm_out, uint32_t* pay_out) {
+  constexpr int N = THREADS * ITEMS;
+  __shared__ K sk[N];
+  __shared__ uint32_t sv[N];
+  __shared__ uint32_t sp[PAY ? N : 1];
+  const uint32_t cnt = w.ctl->class_count[cls];
+  const uint32_t cnt_c = (uint32_t)min((uint64_t)cnt, w.cls_cap[cls]);
+  for (uint32_t q = blockIdx.x; q < cnt_c; q += gridDim.x) {
+    const FinalSeg f = w.cls[cls][q];
+    const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
+    const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
+    const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
+    K k[ITEMS];
+    uint32_t v[ITEMS], p[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      // thread t takes logical elements t*ITEMS+i; load striped for coalescing
+      // and let the first sort round place them (any input order is valid).
+      const uint32_t j = i * THREADS + threadIdx.x;
+      if (j < f.len) {
+        if (f.src) {
+          k[i] = srck[f.start + j];
+          v[i] = srci[f.start + j];
+        } else {
+          k[i] = load_ord<K, F32>(srck, f.start + j);
+          v[i] = j;
+        }
+      } else {
+        k[i] = KMax<K>::v;
+        v[i] = kPadIdx;
+      }
+      p[i] = j;
+    }
+    block_merge_sort<K, THREADS, ITEMS, PAY>(k, v, p, sk, sv, sp);
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      sk[threadIdx.x * ITEMS + i] = k[i];
+      sv[threadIdx.x * ITEMS + i] = v[i];
+      if constexpr (PAY) sp[threadIdx.x * ITEMS + i] = p[i];
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < f.len; j += THREADS) {
+      keys_out[f.start + j] = to_output<K, F32>(sk[j]);
+      if (perm_out) perm_out[f.start + j] = sv[j];
+      if constexpr (PAY) pay_out[f.start + j] = srcp[f.start + sp[j]];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fallback for final segments longer than cap (the balance guarantee of the
+// sampling holds only with high probability): bottom-up merge sort through
+// global memory by one workgroup, ping-ponging between the two buffers over
+// the segment's own range (that range of the other buffer is never used by
+// another segment).  Slow, exact, rare.
+template <typename K>
+struct GRun {
+  const K* k;
+  const uint32_t* v;
+  const uint32_t* p;
+};
+
+template <typename K, bool F32, bool PAY, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_oversize(Work w, const K* in_keys, const uint32_t* in_pay, K* keys_out,
+                                                      uint32_t* perm_out, uint32_t* pay_out) {
+  constexpr int C = THREADS * ITEMS;
+  __shared__ K sk[C];
+  __shared__ uint32_t sv[C];
+  __shared__ uint32_t sp[C];
+  const int cls = kNumClasses - 1;
+  const uint32_t cnt = (uint32_t)min((uint64_t)w.ctl->class_count[cls], w.cls_cap[cls]);
+  for (uint32_t q = blockIdx.x; q < cnt; q += gridDim.x) {
+    const FinalSeg f = w.cls[cls][q];
+    // buffers used: data source code f.src; first target is the other buffer
+    // pass 0 writes into the buffer that does not hold the data
+    int cur = f.src == 0 ? 0 : ((int)f.src - 1) ^ 1;
+    const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
+    const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
+    const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
+    // pass 0: sort chunks of C in LDS
+    for (uint32_t c0 = 0; c0 < f.len; c0 += C) {
+      K k[ITEMS];
+      uint32_t v[ITEMS], p[ITEMS];
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        const uint32_t j = c0 + threadIdx.x * ITEMS + i;
+        if (j < f.len) {
+          k[i] = f.src ? srck[f.start + j] : load_ord<K, F32>(srck, f.start + j);
+          v[i] = f.src ? srci[f.start + j] : j;
+          p[i] = PAY ? srcp[f.start + j] : 0u;
+        } else {
+          k[i] = KMax<K>::v;
+          v[i] = kPadIdx;
+          p[i] = 0;
+        }
+      }
+      block_merge_sort<K, THREADS, ITEMS, PAY>(k, v, p, sk, sv, sp);
+      K* dk = (K*)w.buf_key[cur];
+      uint32_t* dv = w.buf_idx[cur];
+      uint32_t* dp = w.buf_pay[cur];
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        const uint32_t j = c0 + threadIdx.x * ITEMS + i;
+        if (j < f.len) {
+          dk[f.start + j] = k[i];
+          dv[f.start + j] = v[i];
+          if constexpr (PAY) dp[f.start + j] = p[i];
+        }
+      }
+      __syncthreads();
+    }
+    // merge passes
+    for (uint32_t run = C; run < f.len; run <<= 1) {
+      const K* ak = (const K*)w.buf_key[cur] + f.start;
+      const uint32_t* av = w.buf_idx[cur] + f.start;
+      const uint32_t* ap = PAY ? w.buf_pay[cur] + f.start : nullptr;
+      K* dk = (K*)w.buf_key[cur ^ 1] + f.start;
+      uint32_t* dv = w.buf_idx[cur ^ 1] + f.start;
+      uint32_t* dp = PAY ? w.buf_pay[cur ^ 1] + f.start : nullptr;
+      for (uint32_t o0 = 0; o0 < f.len; o0 += THREADS) {
+        const uint32_t o = o0 + threadIdx.x;  // output position handled by this thread
+        if (o < f.len) {
+          const uint32_t first = o / (2 * run) * (2 * run);
+          const uint32_t alen = min(run, f.len - first);
+          const uint32_t b0 = first + alen;
+          const uint32_t blen = b0 < f.len ? min(run, f.len - b0) : 0u;
+          const uint32_t d = o - first;
+          // number of A elements among the first d outputs (ties prefer A)
+          uint32_t lo = d > blen ? d - blen : 0u, hi = d < alen ? d : alen;
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            const uint32_t bj = b0 + d - 1 - mid;
+            if (pair_less(ak[bj], av[bj], ak[first + mid], av[first + mid]))
+              hi = mid;
+            else
+              lo = mid + 1;
+          }
+          const uint32_t ai = lo, bi = d - lo;
+          bool takeA;
+          if (ai >= alen)
+            takeA = false;
+          else if (bi >= blen)
+            takeA = true;
+          else
+            takeA = !pair_less(ak[b0 + bi], av[b0 + bi], ak[first + ai], av[first + ai]);
+          const uint32_t sidx = takeA ? first + ai : b0 + bi;
+          dk[o] = ak[sidx];
+          dv[o] = av[sidx];
+          if constexpr (PAY) dp[o] = ap[sidx];
+        }
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+    // output
+    const K* rk = (const K*)w.buf_key[cur] + f.start;
+    const uint32_t* rv = w.buf_idx[cur] + f.start;
+    const uint32_t* rp = PAY ? w.buf_pay[cur] + f.start : nullptr;
+    for (uint32_t j = threadIdx.x; j < f.len; j += THREADS) {
+      keys_out[f.start + j] = to_output<K, F32>(rk[j]);
+      if (perm_out) perm_out[f.start + j] = rv[j];
+      if constexpr (PAY) pay_out[f.start + j] = rp[j];
+    }
+    __syncthreads();
+  }
+}
+
+// Local sort of one class with the merge sort.
+template <typename K, bool F32, bool PAY>
+int launch_merge_class(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
+                       uint32_t* pay_out, uint64_t cap_c, hipStream_t st) {
+  switch (c) {
+    case 0:
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 64, 1>), grid_for(cap_c, 16), 64, st, w, c, kin, pay_in, kout, perm_out, pay_out);
+      break;
+    case 1:
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 64, 4>), grid_for(cap_c, 16), 64, st, w, c, kin, pay_in, kout, perm_out, pay_out);
+      break;
+    case 2:
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 256, 4>), grid_for(cap_c, 8), 256, st, w, c, kin, pay_in, kout, perm_out,
+                pay_out);
+      break;
+    case 3:
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 256, 8>), grid_for(cap_c, 8), 256, st, w, c, kin, pay_in, kout, perm_out,
+                pay_out);
+      break;
+    case 4:
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 256, 16>), grid_for(cap_c, 4), 256, st, w, c, kin, pay_in, kout, perm_out,
+                pay_out);
+      break;
+    case 5:
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 512, 16>), grid_for(cap_c, 2), 512, st, w, c, kin, pay_in, kout, perm_out,
+                pay_out);
+      break;
+    case 6:
+      if constexpr (!PAY) {
+        RS_LAUNCH((k_local_sort<K, F32, PAY, 768, 16>), grid_for(cap_c, 1), 768, st, w, c, kin, pay_in, kout, perm_out,
+                  pay_out);
+      }
+      break;
+    default:
+      break;
+  }
+  return 0;
+}
+
+#define RS_INST_MERGE(K, F, P)                                                                                 \
+  template int launch_merge_class<K, F, P>(int, const Work&, const K*, const uint32_t*, K*, uint32_t*, uint32_t*, \
+                                           uint64_t, hipStream_t);
+RS_INST_MERGE(uint32_t, false, false)
+RS_INST_MERGE(uint32_t, true, false)
+RS_INST_MERGE(uint64_t, false, false)
+RS_INST_MERGE(uint32_t, false, true)
+RS_INST_MERGE(uint32_t, true, true)
+RS_INST_MERGE(uint64_t, false, true)
+
+
+template <typename K, bool F32, bool PAY>
+int launch_oversize(const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
+                    uint32_t* pay_out, uint64_t cap_c, hipStream_t st) {
+  RS_LAUNCH((k_oversize<K, F32, PAY, 256, 16>), grid_for(cap_c, 1), 256, st, w, kin, pay_in, kout, perm_out, pay_out);
+  return 0;
+}
+
+#define RS_INST_OVER(K, F, P)                                                                                  \
+  template int launch_oversize<K, F, P>(const Work&, const K*, const uint32_t*, K*, uint32_t*, uint32_t*, uint64_t, \
+                                        hipStream_t);
+RS_INST_OVER(uint32_t, false, false)
+RS_INST_OVER(uint32_t, true, false)
+RS_INST_OVER(uint64_t, false, false)
+RS_INST_OVER(uint32_t, false, true)
+RS_INST_OVER(uint32_t, true, true)
+RS_INST_OVER(uint64_t, false, true)
+
+}  // namespace rs

@@ -1,0 +1,148 @@
+"""C-ABI checks that need no GPU: exported symbols, host-side argument
+validation, tuning, workspace sizing and the server's admission logic (fake
+executor)."""
+import ctypes
+import os
+import re
+import time
+
+import pytest
+
+from paper_1606_08766_amd import rsort as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "rsort.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rsort_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_header_function():
+    L = R.lib()
+    names = header_functions()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(names) == sorted(R.EXPORTS)
+
+
+def test_host_validation_without_gpu():
+    L = R.lib()
+    vp = ctypes.c_void_p
+    # n == 0 is a no-op, unknown key type is rejected, NULL pointers rejected
+    assert L.rsort_plain(1, None, 0, None, None, None, 0, None) == R.OK
+    assert L.rsort_plain(7, vp(16), 10, vp(4096), None, vp(1 << 20), 1 << 20, None) == R.EINVAL
+    assert L.rsort_plain(1, None, 10, vp(4096), None, vp(1 << 20), 1 << 20, None) == R.EINVAL
+    assert L.rsort_plain(1, vp(4096), 1 << 32, vp(1 << 40), None, vp(1 << 41), 1 << 20, None) == R.EINVAL
+    # overlapping input and output
+    assert L.rsort_plain(1, vp(4096), 100, vp(4096 + 8), None, vp(1 << 30), 1 << 20, None) == R.EINVAL
+    # workspace too small
+    need = R.plain_workspace_bytes(1, 100000)
+    assert L.rsort_plain(1, vp(1 << 30), 100000, vp(1 << 31), None, vp(1 << 33), need - 1, None) == R.ENOMEM
+    # segmented: empty call, missing offsets, mismatched payload pointers
+    assert L.rsort_segmented(1, None, None, None, 0, 0, None, None, None, None, 0, None) == R.OK
+    assert L.rsort_segmented(1, vp(4096), None, None, 3, 10, vp(1 << 20), None, None, vp(1 << 30), 1 << 20,
+                             None) == R.EINVAL
+    assert L.rsort_segmented(1, vp(4096), vp(1 << 16), vp(1 << 18), 1, 10, vp(1 << 20), None, None, vp(1 << 30),
+                             1 << 20, None) == R.EINVAL
+    assert L.rsort_median_tree(None, 0, None, 0, 3, None, 1, None, None, 0, None) == R.EINVAL
+    assert R.strerror(R.ENOTFOUND) == "unknown ticket"
+
+
+def test_workspace_sizes_monotone():
+    for kt in (R.U32, R.U64, R.F32):
+        prev = 0
+        for n in (1, 100, 12288, 12289, 1 << 20, 1 << 24):
+            b = R.plain_workspace_bytes(kt, n)
+            assert b >= prev
+            prev = b
+    assert R.plain_workspace_bytes(5, 10) == 0
+    assert R.segmented_workspace_bytes(R.U64, 1 << 20, 1000, True) > R.segmented_workspace_bytes(R.U64, 1 << 20, 1000,
+                                                                                                   False)
+    # 2^28 u64 keys: two ping-pong buffers of 12 B/key plus small tables
+    b = R.plain_workspace_bytes(R.U64, 1 << 28)
+    assert 6 << 30 < b < 8 << 30
+
+
+def test_tuning_roundtrip():
+    t0 = R.get_tuning()
+    with R.tuned(oversample=8, tile_log2=13, force_fallback=1):
+        t = R.get_tuning()
+        assert t.oversample == 8 and t.tile_log2 == 13 and t.force_fallback == 1
+    t1 = R.get_tuning()
+    assert (t1.oversample, t1.tile_log2, t1.force_fallback) == (t0.oversample, t0.tile_log2, t0.force_fallback)
+    with pytest.raises(R.RsortError):
+        R.set_tuning(tile_log2=11)
+    with pytest.raises(R.RsortError):
+        R.set_tuning(oversample=33)
+
+
+# ---------------------------------------------------------------- server (fake executor, host only)
+def fake_req(s, n, kt=R.U64, bad=False):
+    return s.submit(kt, 0xBAD if bad else 0x1000, n, 0x100000, None)
+
+
+def test_server_admission_budget_and_tickets():
+    budget = 10 * (1 << 20) * 16  # 10 requests of 2^20 u64 keys (in + out)
+    with R.Server(device=-1, hbm_budget_bytes=budget, max_inflight=4) as s:
+        with pytest.raises(R.RsortError) as e:
+            fake_req(s, budget)  # alone larger than the budget
+        assert e.value.code == R.ENOMEM
+        tickets = [fake_req(s, 1 << 20) for _ in range(12)]
+        assert len(set(tickets)) == 12
+        peak = 0
+        while True:
+            c = s.counters()
+            assert c["bytes_in_use"] <= budget
+            assert c["running"] <= 4
+            peak = max(peak, c["running"])
+            if c["finished"] == 12:
+                break
+            time.sleep(0.0002)
+        assert peak >= 2  # requests overlap
+        for t in tickets:
+            rc, r = s.poll(t)
+            assert rc == R.OK and r.t_submit_ns <= r.t_start_ns <= r.t_done_ns
+        assert s.poll(123456)[0] == R.ENOTFOUND
+        assert s.release(tickets[0]) == R.OK
+        assert s.poll(tickets[0])[0] == R.ENOTFOUND
+
+
+def test_server_fifo_and_memory_wait():
+    per = (1 << 20) * 16
+    with R.Server(device=-1, hbm_budget_bytes=2 * per, max_inflight=8) as s:
+        ts = [fake_req(s, 1 << 20) for _ in range(6)]
+        starts = []
+        for t in ts:
+            rc, r = s.wait(t, 5000)
+            assert rc == R.OK
+            starts.append(r.t_start_ns)
+        assert starts == sorted(starts)  # admitted in arrival order
+        # at most two fit the budget at a time: the third starts after the first ends
+        r0 = s.poll(ts[0])[1]
+        r2 = s.poll(ts[2])[1]
+        assert r2.t_start_ns >= r0.t_done_ns
+
+
+def test_server_error_goes_to_its_ticket_only():
+    with R.Server(device=-1, hbm_budget_bytes=1 << 34, max_inflight=1) as s:
+        good1 = fake_req(s, 1000)
+        bad = fake_req(s, 1000, bad=True)
+        good2 = fake_req(s, 1000)
+        assert s.wait(good1, 5000)[0] == R.OK
+        assert s.wait(bad, 5000)[0] == R.EDEVICE
+        assert s.wait(good2, 5000)[0] == R.OK
+        zero = s.submit(R.U32, 0, 0, 0, None)
+        assert s.poll(zero)[0] == R.OK
+
+
+def test_server_rejects_bad_requests():
+    with R.Server(device=-1, hbm_budget_bytes=1 << 30, max_inflight=2) as s:
+        with pytest.raises(R.RsortError):
+            s.submit(9, 0x1000, 10, 0x2000, None)
+        with pytest.raises(R.RsortError):
+            s.submit(R.U32, 0, 10, 0x2000, None)
+    with pytest.raises(R.RsortError):
+        R.Server(device=-1, hbm_budget_bytes=1 << 30, max_inflight=0)

@@ -143,6 +143,13 @@ def test_f32_total_order_matches_float_compare():
     assert O.ord_f32(0xFFC00001) < O.ord_f32(0xFFC00000) < O.ord_f32(0xFF800000)
 
 
+def test_rank_matches_sort():
+    x = gen.keys("u32", "topbits", 5000, param=4, seed=3)
+    _, po, _ = O.sort(x)
+    for r in (0, 1, 17, 2500, 4999):
+        assert O.rank(x, int(po[r])) == r
+
+
 # ---------------------------------------------------------------- P4
 @pytest.mark.parametrize("kt,dist", [("u64", "uniform"), ("u64", "gaussian"), ("u32", "uniform"),
                                      ("u32", "topbits"), ("u64", "deterdupl")])
