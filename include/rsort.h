@@ -193,6 +193,18 @@ int rsort_server_counters(rsort_server *s, uint64_t *queued, uint64_t *running,
                           uint64_t *finished, uint64_t *bytes_in_use);
 
 /* ------------------------------------------------------------------------
+ * Kernel timing (measurement support, process-wide).  rsort_timing_begin()
+ * starts bracketing every kernel this library launches with HIP events on
+ * the launch's own stream.  rsort_timing_end() stops, synchronises the device
+ * and reports per kernel name (up to max_entries, names truncated to
+ * name_len - 1 characters in the caller's char[max_entries][name_len]) the
+ * number of launches and their summed duration in milliseconds.
+ * ---------------------------------------------------------------------- */
+int rsort_timing_begin(void);
+int rsort_timing_end(uint32_t max_entries, char *names, uint32_t name_len, uint32_t *launches,
+                     double *total_ms, uint32_t *n_entries);
+
+/* ------------------------------------------------------------------------
  * Binary-tree approximate median (paper Section 3.2), computed on the device
  * for num_problems independent problems of p = 2^log2_p leaves each.
  *   vals      device u64 values of all problems back to back (unique within a

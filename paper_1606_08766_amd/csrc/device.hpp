@@ -109,6 +109,26 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, u
   return r;
 }
 
+// Wave-aggregated append: every active lane obtains a slot from
+// counters[key] with one atomic per distinct key per wave.  Must be reached by
+// all lanes of the wave (inactive lanes pass active = false).
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counters, uint32_t key, bool active) {
+  uint32_t slot = 0;
+  const uint32_t lane = lane_id();
+  uint64_t pending = __ballot(active);
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t k = __shfl(key, leader, kWave);
+    const uint64_t m = __ballot(active && key == k) & pending;
+    uint32_t base = 0;
+    if (lane == (uint32_t)leader) base = atomicAdd(&counters[k], (uint32_t)__popcll(m));
+    base = __shfl(base, leader, kWave);
+    if ((m >> lane) & 1ull) slot = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    pending &= ~m;
+  }
+  return slot;
+}
+
 // ---------------------------------------------------------------------------
 // Register sorting network (bitonic) on ITEMS (power of two) pairs, ascending.
 // ---------------------------------------------------------------------------
@@ -236,6 +256,111 @@ __device__ __forceinline__ void block_merge_sort(K (&k)[ITEMS], uint32_t (&v)[IT
           vb = sv[b0 + bi];
         }
       }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Bank-conflict-free LDS merge sort.
+//
+// Elements live in LDS as separate 32-bit arrays (key low word, key high word
+// for u64 keys, position, optional carried value) with one pad word after
+// every 32 words: logical index i is stored at i + i/32.  In the merge rounds
+// lane t reads around logical index t * ITEMS / 2, and in the store phase at
+// t * ITEMS; with the pad both patterns spread a wave over all 32 banks.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+__host__ __device__ constexpr int lpad_size(int n) { return n + (n >> 5) + 1; }
+
+template <typename K>
+struct LdsArr {
+  uint32_t* lo;
+  uint32_t* hi;  // u64 keys only
+  uint32_t* v;
+  uint32_t* p;   // carried value (CARRY only)
+  __device__ __forceinline__ K key(int q) const {
+    if constexpr (sizeof(K) == 8)
+      return ((uint64_t)hi[q] << 32) | lo[q];
+    else
+      return lo[q];
+  }
+  __device__ __forceinline__ void put(int q, K k, uint32_t idx) const {
+    lo[q] = (uint32_t)k;
+    if constexpr (sizeof(K) == 8) hi[q] = (uint32_t)((uint64_t)k >> 32);
+    v[q] = idx;
+  }
+};
+
+template <typename K, int THREADS, int ITEMS, bool CARRY, int GROUP = THREADS>
+__device__ __forceinline__ void lds_merge_sort(K (&k)[ITEMS], uint32_t (&v)[ITEMS], uint32_t (&p)[ITEMS],
+                                               const LdsArr<K>& s) {
+  constexpr int N = THREADS * ITEMS;
+  if constexpr (CARRY)
+    reg_sort3<K, ITEMS>(k, v, p);
+  else
+    reg_sort<K, ITEMS>(k, v);
+  const int t = threadIdx.x;
+#pragma unroll 1
+  for (int run = ITEMS; run < GROUP * ITEMS; run <<= 1) {
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const int q = lpad(t * ITEMS + i);
+      s.put(q, k[i], v[i]);
+      if constexpr (CARRY) s.p[q] = p[i];
+    }
+    __syncthreads();
+    const int first = (t * ITEMS) & ~(2 * run - 1);
+    const int a0 = first, b0 = first + run;
+    const int alen = (N - a0) < run ? (N - a0) : run;
+    const int blen = (N - b0) <= 0 ? 0 : ((N - b0) < run ? (N - b0) : run);
+    const int d = t * ITEMS - first;
+    int lo = d > blen ? d - blen : 0;
+    int hi = d < alen ? d : alen;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      const int qb = lpad(b0 + d - 1 - mid), qa = lpad(a0 + mid);
+      if (pair_less(s.key(qb), s.v[qb], s.key(qa), s.v[qa]))
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    int ai = lo, bi = d - lo;
+    K ka = K(0), kb = K(0);
+    uint32_t va = 0, vb = 0;
+    if (ai < alen) {
+      const int q = lpad(a0 + ai);
+      ka = s.key(q);
+      va = s.v[q];
+    }
+    if (bi < blen) {
+      const int q = lpad(b0 + bi);
+      kb = s.key(q);
+      vb = s.v[q];
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const bool takeA = ai < alen && (bi >= blen || !pair_less(kb, vb, ka, va));
+      k[i] = takeA ? ka : kb;
+      v[i] = takeA ? va : vb;
+      if constexpr (CARRY) p[i] = s.p[lpad(takeA ? a0 + ai : b0 + bi)];
+      // advance the consumed side and fetch its next element
+      const int na = takeA ? ai + 1 : ai, nb = takeA ? bi : bi + 1;
+      const bool more = takeA ? na < alen : nb < blen;
+      if (more) {
+        const int q = lpad(takeA ? a0 + na : b0 + nb);
+        const K nk = s.key(q);
+        const uint32_t nv = s.v[q];
+        if (takeA) {
+          ka = nk;
+          va = nv;
+        } else {
+          kb = nk;
+          vb = nv;
+        }
+      }
+      ai = na;
+      bi = nb;
     }
     __syncthreads();
   }

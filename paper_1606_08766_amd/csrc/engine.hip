@@ -49,14 +49,28 @@ __device__ __forceinline__ uint32_t logk_for(uint32_t len, uint32_t target) {
 
 __device__ __forceinline__ void set_status(Ctl* ctl, int32_t code) { atomicCAS(&ctl->status, 0, code); }
 
-__device__ __forceinline__ void push_final(const Work& w, uint64_t start, uint32_t len, uint32_t src,
-                                           uint32_t cap, uint32_t ff) {
-  const uint32_t c = class_of(len, cap, ff);
-  const uint32_t i = atomicAdd(&w.ctl->class_count[c], 1u);
-  if (i < w.cls_cap[c])
-    w.cls[c][i] = FinalSeg{start, len, src};
-  else
-    set_status(w.ctl, -3);  // capacity bound violated: internal error
+// Append one segment per active lane either to the list of segments the
+// next level splits (to_big) or to the final list of its size class.  Wave
+// aggregated; every lane of the wave must call it.
+__device__ __forceinline__ void route(const Work& w, uint32_t* big_counter, BigSeg* big_list, bool active,
+                                      bool to_big, uint64_t start, uint64_t ubase, uint32_t len, uint32_t src,
+                                      uint32_t cap, uint32_t ff, uint32_t target) {
+  const bool ab = active && to_big, af = active && !to_big;
+  const uint32_t i = wave_append(big_counter, 0u, ab);
+  if (ab) {
+    if (i < w.big_max)
+      big_list[i] = BigSeg{start, ubase, len, logk_for(len, target)};
+    else
+      set_status(w.ctl, -3);  // capacity bound violated: internal error
+  }
+  const uint32_t c = af ? class_of(len, cap, ff) : 0u;
+  const uint32_t j = wave_append(w.ctl->class_count, c, af);
+  if (af) {
+    if (j < w.cls_cap[c])
+      w.cls[c][j] = FinalSeg{start, len, src};
+    else
+      set_status(w.ctl, -3);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -70,25 +84,22 @@ __global__ void k_reset(Ctl* ctl, uint32_t levels) {
 __global__ void k_init(Work w, const uint64_t* seg_off, uint32_t num_segs, uint64_t n_total, uint32_t cap,
                        uint32_t target, uint32_t levels, uint32_t ff) {
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < num_segs; s += stride) {
-    const uint64_t a = seg_off ? seg_off[s] : 0ull;
-    const uint64_t b = seg_off ? seg_off[s + 1] : n_total;
-    if (b < a || b > n_total || (s == 0 && a != 0) || (s + 1 == num_segs && b != n_total) ||
-        b - a >= 0xFFFFFFFFull) {
-      set_status(w.ctl, -1);
-      continue;
+  for (uint32_t s0 = blockIdx.x * blockDim.x; s0 < num_segs; s0 += stride) {
+    const uint32_t s = s0 + threadIdx.x;
+    bool active = s < num_segs;
+    uint64_t a = 0, b = 0;
+    if (active) {
+      a = seg_off ? seg_off[s] : 0ull;
+      b = seg_off ? seg_off[s + 1] : n_total;
+      if (b < a || b > n_total || (s == 0 && a != 0) || (s + 1 == num_segs && b != n_total) ||
+          b - a >= 0xFFFFFFFFull) {
+        set_status(w.ctl, -1);
+        active = false;
+      }
     }
-    const uint32_t len = (uint32_t)(b - a);
-    if (len == 0) continue;
-    if (len > cap && levels > 0) {
-      const uint32_t i = atomicAdd(&w.ctl->big_count[0], 1u);
-      if (i < w.big_max)
-        w.big[0][i] = BigSeg{a, a, len, logk_for(len, target)};
-      else
-        set_status(w.ctl, -3);
-    } else {
-      push_final(w, a, len, 0u, cap, ff);
-    }
+    const uint32_t len = active ? (uint32_t)(b - a) : 0u;
+    active = active && len > 0;
+    route(w, &w.ctl->big_count[0], w.big[0], active, len > cap && levels > 0, a, a, len, 0u, cap, ff, target);
   }
 }
 
@@ -135,9 +146,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev, uint32_t
 template <typename K, bool F32, bool SRC_IN, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K* in_keys, int src_buf,
                                                        uint32_t a, uint64_t seed) {
-  constexpr int N = THREADS * ITEMS;
-  __shared__ K sk[N];
-  __shared__ uint32_t sv[N];
+  constexpr int NP = lpad_size(THREADS * ITEMS);
+  __shared__ uint32_t s_lo[NP];
+  __shared__ uint32_t s_hi[sizeof(K) == 8 ? NP : 1];
+  __shared__ uint32_t s_v[NP];
+  const LdsArr<K> sa{s_lo, s_hi, s_v, nullptr};
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
   const K* bkey = SRC_IN ? nullptr : (const K*)w.buf_key[src_buf];
@@ -167,12 +180,9 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
       }
       p[i] = 0;
     }
-    block_merge_sort<K, THREADS, ITEMS, false>(k, v, p, sk, sv, nullptr);
+    lds_merge_sort<K, THREADS, ITEMS, false>(k, v, p, sa);
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      sk[threadIdx.x * ITEMS + i] = k[i];
-      sv[threadIdx.x * ITEMS + i] = v[i];
-    }
+    for (int i = 0; i < ITEMS; i++) sa.put(lpad(threadIdx.x * ITEMS + i), k[i], v[i]);
     __syncthreads();
     const uint32_t kk = 1u << bs.logk;
     for (uint32_t node = threadIdx.x + 1; node < kk; node += THREADS) {
@@ -180,13 +190,13 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
       const uint32_t q = node - (1u << d);
       const uint32_t j = (2u * q + 1u) << (bs.logk - 1u - d);
       const uint32_t r = j * a - 1u;
-      tkey[(uint64_t)s * kMaxK + node] = sk[r];
-      w.tree_idx[(uint64_t)s * kMaxK + node] = sv[r];
+      tkey[(uint64_t)s * kMaxK + node] = sa.key(lpad(r));
+      w.tree_idx[(uint64_t)s * kMaxK + node] = s_v[lpad(r)];
     }
     if (lev == 0 && s == 0) {
       for (uint32_t j = threadIdx.x + 1; j < kk; j += THREADS) {
-        w.ctl->l0_spl_key[j - 1] = (uint64_t)sk[j * a - 1u];
-        w.ctl->l0_spl_pos[j - 1] = sv[j * a - 1u];
+        w.ctl->l0_spl_key[j - 1] = (uint64_t)sa.key(lpad(j * a - 1u));
+        w.ctl->l0_spl_pos[j - 1] = s_v[lpad(j * a - 1u)];
       }
       if (threadIdx.x == 0) w.ctl->l0_k = kk;
     }
@@ -450,33 +460,41 @@ __global__ void k_level_end(Work w, int lev, uint32_t cap, uint32_t target, int 
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
   const uint64_t total = (uint64_t)m * kMaxK;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
-    const uint32_t s = (uint32_t)(g / kMaxK), b = (uint32_t)(g % kMaxK);
-    const BigSeg bs = w.big[cur][s];
-    const uint32_t kk = 1u << bs.logk;
-    if (b >= kk) continue;
-    const uint32_t nt = w.tile_base[s + 1] - w.tile_base[s];
-    const uint32_t cb = w.count_base[s];
-    const uint32_t seg0 = w.offsets[cb];
-    const uint32_t lo = w.offsets[cb + b * nt] - seg0;
-    const uint32_t hi = (b + 1 < kk) ? w.offsets[cb + (b + 1) * nt] - seg0 : bs.len;
-    const uint32_t len = hi - lo;
-    if (lev == 0 && s == 0) w.ctl->l0_bucket[b] = len;
+  for (uint64_t g0 = (uint64_t)blockIdx.x * blockDim.x; g0 < total; g0 += stride) {
+    const uint64_t g = g0 + threadIdx.x;
+    bool active = g < total;
+    const uint32_t s = active ? (uint32_t)(g / kMaxK) : 0u, b = (uint32_t)(g % kMaxK);
+    BigSeg bs{0, 0, 0, 1};
+    uint32_t len = 0, lo = 0;
+    if (active) {
+      bs = w.big[cur][s];
+      const uint32_t kk = 1u << bs.logk;
+      active = b < kk;
+      if (active) {
+        const uint32_t nt = w.tile_base[s + 1] - w.tile_base[s];
+        const uint32_t cb = w.count_base[s];
+        const uint32_t seg0 = w.offsets[cb];
+        lo = w.offsets[cb + b * nt] - seg0;
+        const uint32_t hi = (b + 1 < kk) ? w.offsets[cb + (b + 1) * nt] - seg0 : bs.len;
+        len = hi - lo;
+        if (lev == 0 && s == 0) w.ctl->l0_bucket[b] = len;
+      }
+    }
     if (lev < kMaxLevels) {
-      atomicMax(&w.ctl->level_max[lev], len);
-      if (len) atomicAdd(&w.ctl->level_buckets[lev], 1u);
+      // per-wave maximum and count, then one atomic per wave
+      uint32_t mx = len, nz = (active && len) ? 1u : 0u;
+      for (int d = kWave / 2; d > 0; d >>= 1) {
+        mx = max(mx, (uint32_t)__shfl_xor(mx, d, kWave));
+        nz += (uint32_t)__shfl_xor(nz, d, kWave);
+      }
+      if (lane_id() == 0) {
+        if (mx) atomicMax(&w.ctl->level_max[lev], mx);
+        if (nz) atomicAdd(&w.ctl->level_buckets[lev], nz);
+      }
     }
-    if (len == 0) continue;
-    const uint64_t start = bs.start + lo;
-    if (len > cap && !last) {
-      const uint32_t i = atomicAdd(&w.ctl->big_count[cur ^ 1], 1u);
-      if (i < w.big_max)
-        w.big[cur ^ 1][i] = BigSeg{start, bs.ubase, len, logk_for(len, target)};
-      else
-        set_status(w.ctl, -3);
-    } else {
-      push_final(w, start, len, dst_code, cap, ff);
-    }
+    active = active && len > 0;
+    route(w, &w.ctl->big_count[cur ^ 1], w.big[cur ^ 1], active, len > cap && !last, bs.start + lo, bs.ubase, len,
+          dst_code, cap, ff, target);
   }
 }
 
@@ -600,14 +618,10 @@ static inline uint32_t grid_for(uint64_t work, uint32_t per_cu) {
   return (uint32_t)std::max<uint64_t>(g, 1);
 }
 
-#define RS_LAUNCH(kern, grid, block, stream, ...)                                      \
-  do {                                                                                 \
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (hipStream_t)(stream), __VA_ARGS__); \
-    if (hipPeekAtLastError() != hipSuccess) return -3;                                 \
-  } while (0)
+
 
 constexpr int kCntThreads = 256;
-constexpr int kSplThreads = 512, kSplItems = 16;  // up to 8192 samples (a = 32, k = 256)
+constexpr int kSplThreads = 1024, kSplItems = 8;  // up to 8192 samples (a = 32, k = 256)
 
 // Algorithm of each size class: RFIS, RQuick or the LDS merge sort.
 template <typename K, bool F32, bool PAY>

@@ -10,12 +10,12 @@
 namespace rs {
 
 struct Tuning {
-  uint32_t oversample = 16;   // samples per bucket
+  uint32_t oversample = 32;   // samples per bucket
   uint32_t target = 4096;     // bucket size a level aims for
   uint32_t cap = 12288;       // largest bucket sorted in LDS
   uint32_t max_levels = 4;
-  uint32_t rfis_max = 1024;   // classes with upper bound <= rfis_max use RFIS
-  uint32_t rquick_max = 4096; // classes with upper bound <= rquick_max use RQuick
+  uint32_t rfis_max = 256;    // classes with upper bound <= rfis_max use RFIS
+  uint32_t rquick_max = 1;    // classes with upper bound <= rquick_max use RQuick
   uint64_t seed = 0x5EED5EED12345678ull;
   uint32_t tile_log2 = 12;
   uint32_t force_fallback = 0;
@@ -56,3 +56,20 @@ int enqueue_median_tree(const uint64_t* vals, uint64_t per_problem, const uint64
 uint32_t num_cu_cached();
 
 }  // namespace rs
+
+namespace rs {
+// Kernel timing (measurement support): when enabled, every launch made
+// through RS_LAUNCH is bracketed by HIP events on its stream.
+bool timing_enabled();
+void timing_before(hipStream_t st);
+void timing_after(const char* tag, hipStream_t st);
+}  // namespace rs
+
+#define RS_LAUNCH(kern, grid, block, stream, ...)                                             \
+  do {                                                                                        \
+    const bool rs_t_ = ::rs::timing_enabled();                                                \
+    if (rs_t_) ::rs::timing_before((hipStream_t)(stream));                                    \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (hipStream_t)(stream), __VA_ARGS__); \
+    if (hipPeekAtLastError() != hipSuccess) return -3;                                        \
+    if (rs_t_) ::rs::timing_after(#kern, (hipStream_t)(stream));                              \
+  } while (0)

@@ -15,11 +15,7 @@ static inline uint32_t grid_for(uint64_t work, uint32_t per_cu) {
   return (uint32_t)std::max<uint64_t>(g, 1);
 }
 
-#define RS_LAUNCH(kern, grid, block, stream, ...)                                             \
-  do {                                                                                        \
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (hipStream_t)(stream), __VA_ARGS__); \
-    if (hipPeekAtLastError() != hipSuccess) return -3;                                        \
-  } while (0)
+
 
 // ---------------------------------------------------------------------------
 // Final segments of one size class: one workgroup each, sorted in LDS.
@@ -27,9 +23,12 @@ template <typename K, bool F32, bool PAY, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K* in_keys, const uint32_t* in_pay,
                                                         K* keys_out, uint32_t* perm_out, uint32_t* pay_out) {
   constexpr int N = THREADS * ITEMS;
-  __shared__ K sk[N];
-  __shared__ uint32_t sv[N];
-  __shared__ uint32_t sp[PAY ? N : 1];
+  constexpr int NP = lpad_size(N);
+  __shared__ uint32_t s_lo[NP];
+  __shared__ uint32_t s_hi[sizeof(K) == 8 ? NP : 1];
+  __shared__ uint32_t s_v[NP];
+  __shared__ uint32_t s_p[PAY ? NP : 1];
+  const LdsArr<K> sa{s_lo, s_hi, s_v, s_p};
   const uint32_t cnt = w.ctl->class_count[cls];
   const uint32_t cnt_c = (uint32_t)min((uint64_t)cnt, w.cls_cap[cls]);
   for (uint32_t q = blockIdx.x; q < cnt_c; q += gridDim.x) {
@@ -58,18 +57,19 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
       }
       p[i] = j;
     }
-    block_merge_sort<K, THREADS, ITEMS, PAY>(k, v, p, sk, sv, sp);
+    lds_merge_sort<K, THREADS, ITEMS, PAY>(k, v, p, sa);
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
-      sk[threadIdx.x * ITEMS + i] = k[i];
-      sv[threadIdx.x * ITEMS + i] = v[i];
-      if constexpr (PAY) sp[threadIdx.x * ITEMS + i] = p[i];
+      const int q = lpad(threadIdx.x * ITEMS + i);
+      sa.put(q, k[i], v[i]);
+      if constexpr (PAY) s_p[q] = p[i];
     }
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < f.len; j += THREADS) {
-      keys_out[f.start + j] = to_output<K, F32>(sk[j]);
-      if (perm_out) perm_out[f.start + j] = sv[j];
-      if constexpr (PAY) pay_out[f.start + j] = srcp[f.start + sp[j]];
+      const int q = lpad(j);
+      keys_out[f.start + j] = to_output<K, F32>(sa.key(q));
+      if (perm_out) perm_out[f.start + j] = s_v[q];
+      if constexpr (PAY) pay_out[f.start + j] = srcp[f.start + s_p[q]];
     }
     __syncthreads();
   }
@@ -213,11 +213,11 @@ int launch_merge_class(int c, const Work& w, const K* kin, const uint32_t* pay_i
                 pay_out);
       break;
     case 4:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 256, 16>), grid_for(cap_c, 4), 256, st, w, c, kin, pay_in, kout, perm_out,
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 512, 8>), grid_for(cap_c, 3), 512, st, w, c, kin, pay_in, kout, perm_out,
                 pay_out);
       break;
     case 5:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 512, 16>), grid_for(cap_c, 2), 512, st, w, c, kin, pay_in, kout, perm_out,
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 1024, 8>), grid_for(cap_c, 1), 1024, st, w, c, kin, pay_in, kout, perm_out,
                 pay_out);
       break;
     case 6:

@@ -112,17 +112,16 @@ int enqueue_median_tree(const uint64_t* vals, uint64_t per_problem, const uint64
   MWin* w1 = w0 + p * num_problems * k;
   const uint32_t cu = num_cu_cached();
   auto grid = [&](uint64_t work) { return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((work + 255) / 256, cu * 8ull)); };
-  hipLaunchKernelGGL(k_med_leaf, dim3(grid(p * num_problems)), dim3(256), 0, st, vals, per_problem, leaf_off, log2_p,
-                     k, coins, num_problems, w0, status);
+  RS_LAUNCH(k_med_leaf, grid(p * num_problems), 256, st, vals, per_problem, leaf_off, log2_p, k, coins, num_problems,
+            w0, status);
   MWin* a = w0;
   MWin* b = w1;
   for (uint64_t parents = p / 2; parents >= 1; parents /= 2) {
-    hipLaunchKernelGGL(k_med_merge, dim3(grid(parents * num_problems * 2 * k)), dim3(256), 0, st, a, b, parents,
-                       num_problems, k);
+    RS_LAUNCH(k_med_merge, grid(parents * num_problems * 2 * k), 256, st, a, b, parents, num_problems, k);
     std::swap(a, b);
   }
-  hipLaunchKernelGGL(k_med_root, dim3(grid(num_problems)), dim3(256), 0, st, a, coins, p, num_problems, k, out);
-  return hipPeekAtLastError() == hipSuccess ? 0 : -3;
+  RS_LAUNCH(k_med_root, grid(num_problems), 256, st, a, coins, p, num_problems, k, out);
+  return 0;
 }
 
 }  // namespace rs

@@ -131,24 +131,22 @@ template <typename K, bool F32, bool PAY>
 int launch_rfis_class(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
                       uint32_t* pay_out, uint64_t cap_c, hipStream_t st) {
   const uint64_t slots = (uint64_t)num_cu_cached() * 16;
+  const uint32_t g1 = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots);
+  const uint32_t g2 = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots / 2);
   switch (c) {
     case 0:
-      hipLaunchKernelGGL((k_rfis<K, F32, PAY, 64, 64>), dim3((uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots)),
-                         dim3(64), 0, st, w, c, kin, pay_in, kout, perm_out, pay_out);
+      RS_LAUNCH((k_rfis<K, F32, PAY, 64, 64>), g1, 64, st, w, c, kin, pay_in, kout, perm_out, pay_out);
       break;
     case 1:
-      hipLaunchKernelGGL((k_rfis<K, F32, PAY, 64, 256>), dim3((uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots)),
-                         dim3(64), 0, st, w, c, kin, pay_in, kout, perm_out, pay_out);
+      RS_LAUNCH((k_rfis<K, F32, PAY, 64, 256>), g1, 64, st, w, c, kin, pay_in, kout, perm_out, pay_out);
       break;
     case 2:
-      hipLaunchKernelGGL((k_rfis<K, F32, PAY, 256, 1024>),
-                         dim3((uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots / 2)), dim3(256), 0, st, w, c,
-                         kin, pay_in, kout, perm_out, pay_out);
+      RS_LAUNCH((k_rfis<K, F32, PAY, 256, 1024>), g2, 256, st, w, c, kin, pay_in, kout, perm_out, pay_out);
       break;
     default:
       return launch_merge_class<K, F32, PAY>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, st);
   }
-  return hipPeekAtLastError() == hipSuccess ? 0 : -3;
+  return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -420,17 +418,15 @@ int launch_rquick_class(int c, const Work& w, const K* kin, const uint32_t* pay_
   const uint32_t g = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots);
   switch (c) {
     case 3:
-      hipLaunchKernelGGL((k_rquick<K, F32, PAY, 512, 2048, 16>), dim3(g), dim3(512), 0, st, w, c, kin, pay_in, kout,
-                         perm_out, pay_out, seed);
+      RS_LAUNCH((k_rquick<K, F32, PAY, 512, 2048, 16>), g, 512, st, w, c, kin, pay_in, kout, perm_out, pay_out, seed);
       break;
     case 4:
-      hipLaunchKernelGGL((k_rquick<K, F32, PAY, 1024, 4096, 16>), dim3(g), dim3(1024), 0, st, w, c, kin, pay_in, kout,
-                         perm_out, pay_out, seed);
+      RS_LAUNCH((k_rquick<K, F32, PAY, 1024, 4096, 16>), g, 1024, st, w, c, kin, pay_in, kout, perm_out, pay_out, seed);
       break;
     default:
       return launch_merge_class<K, F32, PAY>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, st);
   }
-  return hipPeekAtLastError() == hipSuccess ? 0 : -3;
+  return 0;
 }
 
 #define RS_INST_SMALL(K, F, P)                                                                                  \

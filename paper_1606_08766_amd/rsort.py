@@ -24,7 +24,8 @@ EXPORTS = [
     "rsort_strerror", "rsort_version", "rsort_plain_workspace", "rsort_plain", "rsort_segmented_workspace",
     "rsort_segmented", "rsort_workspace_status", "rsort_stats", "rsort_get_tuning", "rsort_set_tuning",
     "rsort_server_create", "rsort_server_destroy", "rsort_submit", "rsort_poll", "rsort_wait", "rsort_release",
-    "rsort_server_counters", "rsort_median_tree_workspace", "rsort_median_tree",
+    "rsort_server_counters", "rsort_median_tree_workspace", "rsort_median_tree", "rsort_timing_begin",
+    "rsort_timing_end",
 ]
 
 
@@ -97,6 +98,9 @@ def lib():
         L.rsort_release.argtypes = [vp, u64]
         L.rsort_server_counters.restype = i32
         L.rsort_server_counters.argtypes = [vp] + [ctypes.POINTER(u64)] * 4
+        L.rsort_timing_begin.restype = i32
+        L.rsort_timing_end.restype = i32
+        L.rsort_timing_end.argtypes = [u32, vp, u32, vp, vp, ctypes.POINTER(u32)]
         L.rsort_median_tree_workspace.restype = sz
         L.rsort_median_tree_workspace.argtypes = [u32, u32, u32]
         L.rsort_median_tree.restype = i32
@@ -250,6 +254,30 @@ class tuned:
         set_tuning(oversample=s.oversample, target=s.target, cap=s.cap, max_levels=s.max_levels,
                    rfis_max=s.rfis_max, rquick_max=s.rquick_max, seed=s.seed, tile_log2=s.tile_log2,
                    force_fallback=1 if s.force_fallback else 2)
+
+
+# ----------------------------------------------------------------------------- timing
+def timing_begin():
+    _check(lib().rsort_timing_begin(), "rsort_timing_begin")
+
+
+def timing_end(max_entries: int = 128) -> dict:
+    """Stop kernel timing; returns {kernel name: (launches, total ms)}."""
+    import numpy as np
+
+    name_len = 160
+    names = ctypes.create_string_buffer(max_entries * name_len)
+    launches = np.zeros(max_entries, np.uint32)
+    ms = np.zeros(max_entries, np.float64)
+    n = ctypes.c_uint32()
+    _check(lib().rsort_timing_end(max_entries, names, name_len, launches.ctypes.data, ms.ctypes.data,
+                                  ctypes.byref(n)), "rsort_timing_end")
+    out = {}
+    raw = names.raw
+    for i in range(n.value):
+        nm = raw[i * name_len:(i + 1) * name_len].split(b"\0", 1)[0].decode()
+        out[nm] = (int(launches[i]), float(ms[i]))
+    return out
 
 
 # ----------------------------------------------------------------------------- median tree

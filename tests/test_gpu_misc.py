@@ -1,0 +1,120 @@
+"""GPU checks of the classification step, balance, tuning invariance, the
+device median tree and the server."""
+import numpy as np
+import pytest
+import torch
+
+from gen import gen
+from oracle import oracle as O
+from paper_1606_08766_amd import rsort as R
+from tests.gpu_util import banner, dev, gpu_sort, host, same_bits
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("kt,dist", [("u64", "uniform"), ("u64", "zero"), ("u64", "deterdupl"), ("u32", "topbits"),
+                                     ("f32", "uniform")])
+def test_level0_buckets_match_oracle_classification(kt, dist):
+    """The level-0 bucket sizes the GPU produced equal the oracle's histogram of
+    classifying every input element against the GPU's splitters with the
+    positional tie-break."""
+    n = (1 << 22) + 17
+    x = gen.keys(kt, dist, n, seed=2, param=3 if dist == "topbits" else 0)
+    banner("level-0 classification %s %s" % (kt, dist))
+    ws = torch.empty(R.plain_workspace_bytes(R.KT_OF_DTYPE[torch.from_numpy(x[:0]).dtype], n), dtype=torch.uint8,
+                     device="cuda")
+    ko, po = R.sort(dev(x), workspace=ws)
+    st = R.stats(ws)
+    assert st["status"] == 0 and st["k"] == 256 and st["levels"] >= 1
+    sk = st["splitter_keys"]
+    if kt == "u64":
+        skeys = sk.astype(np.uint64)
+        xin = x
+    else:  # ordinal u32 keys: compare as ordinals
+        skeys = sk.astype(np.uint32)
+        xin = x.view(np.uint32)
+        if kt == "f32":
+            b = xin
+            xin = np.where(b >> np.uint32(31) == 1, ~b, b | np.uint32(0x80000000)).astype(np.uint32)
+    bucket = O.classify(xin, None, skeys, st["splitter_pos"])
+    hist = np.bincount(bucket, minlength=256)
+    assert np.array_equal(hist, st["bucket_sizes"].astype(np.int64))
+    assert st["bucket_sizes"].sum() == n
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zero", "deterdupl", "reverse", "gaussian"])
+def test_balance_per_level(dist):
+    """Positional tie-breaking splits duplicates evenly: the largest bucket of
+    each level stays within a small factor of the average for every input."""
+    n = 1 << 24
+    x = gen.keys("u64", dist, n, seed=1)
+    ws = torch.empty(R.plain_workspace_bytes(R.U64, n), dtype=torch.uint8, device="cuda")
+    banner("balance %s" % dist)
+    R.sort(dev(x), workspace=ws)
+    st = R.stats(ws)
+    assert st["oversize"] == 0
+    avg0 = n / 256
+    assert st["level_max"][0] < 2.5 * avg0
+    assert st["level_buckets"][0] == 256  # no bucket empty: ties split by position
+
+
+@pytest.mark.parametrize("tune", [dict(oversample=4), dict(oversample=32), dict(tile_log2=13), dict(cap=4096),
+                                  dict(target=1024), dict(max_levels=1), dict(seed=12345)])
+def test_tuning_does_not_change_output(tune):
+    x = gen.keys("u64", "deterdupl", 5_000_003, seed=3, param=1000)
+    ek, ep, _ = O.sort(x, threads=4)
+    with R.tuned(**tune):
+        ko, po = gpu_sort(x)
+    assert same_bits(ko, ek) and np.array_equal(po, ep)
+
+
+@pytest.mark.parametrize("log2_p,k,per_leaf", [(0, 2, 6), (3, 2, 2), (5, 4, 3), (8, 8, 2), (10, 2, 1), (6, 16, 5)])
+def test_median_tree_matches_oracle(log2_p, k, per_leaf):
+    p = 1 << log2_p
+    rng = np.random.default_rng(log2_p * 100 + k)
+    problems = 64
+    per_problem = p * per_leaf + 3
+    vals = np.empty(problems * per_problem, dtype=np.uint64)
+    offs = np.empty(problems * (p + 1), dtype=np.uint64)
+    coins = rng.integers(0, 2, size=problems * (p + 1)).astype(np.uint8)
+    expect = []
+    for q in range(problems):
+        v = rng.choice(1 << 40, size=per_problem, replace=False).astype(np.uint64)
+        sizes = rng.integers(0, 2 * per_leaf + 1, size=p)
+        sizes = np.minimum(sizes, 64)
+        o = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+        o = np.minimum(o, per_problem)
+        vals[q * per_problem:(q + 1) * per_problem] = v
+        offs[q * (p + 1):(q + 1) * (p + 1)] = o
+        expect.append(O.median_tree(v, o, log2_p, k, coins[q * (p + 1):(q + 1) * (p + 1)]))
+    banner("median tree p=%d k=%d" % (p, k))
+    out = host(R.median_tree(dev(vals), per_problem, dev(offs), log2_p, k, dev(coins), problems))
+    for q in range(problems):
+        v, side = expect[q]
+        gside = {0: 0, 1: -1, 2: 1}[int(out[q, 1])]
+        assert gside == side
+        if side == 0:
+            assert int(out[q, 0]) == v
+
+
+def test_server_alone_equals_mix():
+    """Each request's output in a busy mix equals its output sorted alone."""
+    rng = np.random.default_rng(5)
+    reqs = []
+    for i in range(40):
+        kt = ["u32", "u64", "f32"][i % 3]
+        n = int(2 ** rng.uniform(8, 21))
+        dist = ["uniform", "gaussian", "zero", "deterdupl", "reverse"][i % 5]
+        reqs.append(gen.keys(kt, dist, n, seed=100 + i))
+    alone = [gpu_sort(x) for x in reqs]
+    banner("server mix of %d requests" % len(reqs))
+    ins = [dev(x) for x in reqs]
+    outs = [(torch.empty_like(t), torch.empty(t.numel(), dtype=torch.uint32, device="cuda")) for t in ins]
+    torch.cuda.synchronize()
+    with R.Server(device=0, hbm_budget_bytes=8 << 30, max_inflight=6) as s:
+        tickets = [s.submit_tensors(t, o[0], o[1]) for t, o in zip(ins, outs)]
+        results = [s.wait(t, 60000) for t in tickets]
+    assert all(rc == R.OK for rc, _ in results), [rc for rc, _ in results]
+    assert max(r.batch_size for _, r in results) >= 1
+    for (ak, ap), (ok, op) in zip(alone, outs):
+        assert same_bits(ak, host(ok)) and np.array_equal(ap, host(op))
