@@ -119,14 +119,21 @@ def bench_plain(args, R, torch):
     for s in range(args.warmup):
         R.sort(inputs[s % len(DISTS)], workspace=ws, out=(ko, po))
     torch.cuda.synchronize()
+    # per-distribution time (events around each step; reported, not the metric)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     R.timing_begin()
     t0 = time.perf_counter()
-    per_dist_t = {d: 0.0 for d in DISTS}
     for s in range(args.steps):
+        ev[s][0].record()
         R.sort(inputs[s % len(DISTS)], workspace=ws, out=(ko, po))
+        ev[s][1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     timing = R.timing_end()
+    per_dist = {}
+    for s in range(args.steps):
+        per_dist.setdefault(DISTS[s % len(DISTS)], []).append(ev[s][0].elapsed_time(ev[s][1]))
+    per_dist = {d: round(n / (sum(v) / len(v) / 1e3) / 1e9, 3) for d, v in per_dist.items()}
     st = R.stats(ws)
     if st["status"] != 0:
         raise RuntimeError("device status %d" % st["status"])
@@ -188,6 +195,7 @@ def bench_plain(args, R, torch):
                    "n": n, "levels": int(st["levels"]), "key_bytes": ks, "perm": True},
         "roofline": roof,
         "passes": passes,
+        "gkeys_per_s_by_distribution": per_dist,
         "hbm_bytes_per_key_algorithmic": sum(bpk.values()),
     }
     return out

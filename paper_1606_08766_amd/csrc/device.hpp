@@ -131,9 +131,20 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t* counters, uint32_t key
 
 // ---------------------------------------------------------------------------
 // Register sorting network (bitonic) on ITEMS (power of two) pairs, ascending.
+// The compare-exchange swaps with a mask and XORs rather than selecting
+// between two array elements: a select of two array loads can be folded into
+// a load at a select-computed index, which keeps the arrays out of registers.
 // ---------------------------------------------------------------------------
-template <typename K, int ITEMS>
-__device__ __forceinline__ void reg_sort(K (&k)[ITEMS], uint32_t (&v)[ITEMS]) {
+template <typename K>
+__device__ __forceinline__ void cx_swap(K& a, K& b, bool sw) {
+  const K m = (K)0 - (K)(sw ? 1 : 0);
+  const K x = (a ^ b) & m;
+  a ^= x;
+  b ^= x;
+}
+
+template <typename K, int ITEMS, bool CARRY>
+__device__ __forceinline__ void reg_sort_impl(K (&k)[ITEMS], uint32_t (&v)[ITEMS], uint32_t (&p)[ITEMS]) {
 #pragma unroll
   for (int size = 2; size <= ITEMS; size <<= 1) {
 #pragma unroll
@@ -143,45 +154,28 @@ __device__ __forceinline__ void reg_sort(K (&k)[ITEMS], uint32_t (&v)[ITEMS]) {
         const int j = i ^ stride;
         if (j > i) {
           const bool asc = (i & size) == 0;
-          const bool sw = asc ? pair_less(k[j], v[j], k[i], v[i]) : pair_less(k[i], v[i], k[j], v[j]);
-          K tk = sw ? k[j] : k[i];
-          uint32_t tv = sw ? v[j] : v[i];
-          k[j] = sw ? k[i] : k[j];
-          v[j] = sw ? v[i] : v[j];
-          k[i] = tk;
-          v[i] = tv;
+          // ascending: the smaller pair ends at i
+          const bool jl = pair_less(k[j], v[j], k[i], v[i]);
+          const bool sw = asc ? jl : !jl;
+          cx_swap(k[i], k[j], sw);
+          cx_swap(v[i], v[j], sw);
+          if constexpr (CARRY) cx_swap(p[i], p[j], sw);
         }
       }
     }
   }
 }
 
+template <typename K, int ITEMS>
+__device__ __forceinline__ void reg_sort(K (&k)[ITEMS], uint32_t (&v)[ITEMS]) {
+  uint32_t p[ITEMS];
+  reg_sort_impl<K, ITEMS, false>(k, v, p);
+}
+
 // Same network carrying a third value.
 template <typename K, int ITEMS>
 __device__ __forceinline__ void reg_sort3(K (&k)[ITEMS], uint32_t (&v)[ITEMS], uint32_t (&p)[ITEMS]) {
-#pragma unroll
-  for (int size = 2; size <= ITEMS; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-#pragma unroll
-      for (int i = 0; i < ITEMS; i++) {
-        const int j = i ^ stride;
-        if (j > i) {
-          const bool asc = (i & size) == 0;
-          const bool sw = asc ? pair_less(k[j], v[j], k[i], v[i]) : pair_less(k[i], v[i], k[j], v[j]);
-          K tk = sw ? k[j] : k[i];
-          uint32_t tv = sw ? v[j] : v[i];
-          uint32_t tp = sw ? p[j] : p[i];
-          k[j] = sw ? k[i] : k[j];
-          v[j] = sw ? v[i] : v[j];
-          p[j] = sw ? p[i] : p[j];
-          k[i] = tk;
-          v[i] = tv;
-          p[i] = tp;
-        }
-      }
-    }
-  }
+  reg_sort_impl<K, ITEMS, true>(k, v, p);
 }
 
 // ---------------------------------------------------------------------------

@@ -204,18 +204,62 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
   }
 }
 
-// Classification with positional tie-break: bucket = number of splitters
-// strictly below (key, idx).
-template <typename K>
-__device__ __forceinline__ uint32_t classify(const K* tk, const uint32_t* ti, uint32_t logk, K key,
-                                             uint32_t idx) {
-  uint32_t j = 1;
+// ---------------------------------------------------------------------------
+// Classification of a thread's ITEMS elements with the splitter tree in LDS
+// (node t of the implicit tree at tk[t] / ti[t]).  Levels are the outer loop
+// so the ITEMS lookups of a level are independent.  The descent compares keys
+// only; an element whose key equals the key of a splitter on its path is
+// classified again comparing (key, position) pairs (the tie-break of
+// Appendix G: positions are looked at only when keys are equal).
+// Result: bucket = number of splitters strictly below (key, position).
+template <typename K, int ITEMS, typename IdxFn>
+__device__ __forceinline__ void classify_batch(const K* tk, const uint32_t* ti, uint32_t logk, const K (&key)[ITEMS],
+                                               const bool (&valid)[ITEMS], IdxFn idx_of, uint32_t (&b)[ITEMS]) {
+  uint32_t j[ITEMS];
+  bool eq[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) j[i] = 1;
   for (uint32_t l = 0; l < logk; l++) {
-    const K t = tk[j];
-    const uint32_t u = ti[j];
-    j = 2u * j + ((key > t) | ((key == t) & (idx > u)) ? 1u : 0u);
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) j[i] = 2u * j[i] + (key[i] > tk[j[i]] ? 1u : 0u);
   }
-  return j - (1u << logk);
+  // A key can only equal a splitter key on its path if it equals the splitter
+  // at the path's last left turn (the smallest splitter key >= key).  The
+  // direction bits of j are the bits below its leading one; the last left
+  // turn is its lowest zero bit z, at node j >> (z + 1).
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    const uint32_t z = (uint32_t)__builtin_ctz(~j[i]);
+    eq[i] = z < logk && key[i] == tk[j[i] >> (z + 1)];
+  }
+  bool tie = false;
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    eq[i] = eq[i] & valid[i];
+    tie = tie | eq[i];
+  }
+  if (__any(tie)) {
+    // positions of the tied elements first (independent loads), then a
+    // level-major descent comparing (key, position)
+    uint32_t id[ITEMS], q[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      id[i] = eq[i] ? idx_of(i) : 0u;
+      q[i] = 1;
+    }
+    for (uint32_t l = 0; l < logk; l++) {
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        const K t = tk[q[i]];
+        const uint32_t u = ti[q[i]];
+        q[i] = 2u * q[i] + ((key[i] > t) | ((key[i] == t) & (id[i] > u)) ? 1u : 0u);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) j[i] = eq[i] ? q[i] : j[i];
+  }
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) b[i] = j[i] - (1u << logk);
 }
 
 __device__ __forceinline__ uint32_t find_seg(const uint32_t* base, uint32_t m, uint32_t tile) {
@@ -230,56 +274,129 @@ __device__ __forceinline__ uint32_t find_seg(const uint32_t* base, uint32_t m, u
   return lo;
 }
 
+// XCD-aware tile order: workgroups are dispatched round-robin over the 8
+// XCDs, so workgroup g runs on XCD g % 8.  Each XCD owns a contiguous range
+// of tiles and each of its workgroups a contiguous sub-range: neighbouring
+// tiles write neighbouring parts of each bucket's output run (which then meet
+// in the same L2), and consecutive tiles of a workgroup mostly belong to the
+// same segment, whose splitter tree then stays in LDS.
+struct TileWalk {
+  uint32_t next, end;
+  __device__ __forceinline__ TileWalk(uint32_t T) {
+    const uint32_t x = blockIdx.x & 7u, r = blockIdx.x >> 3, per = max(gridDim.x >> 3, 1u);
+    const uint64_t lo = ((uint64_t)T * x) >> 3, hi = ((uint64_t)T * (x + 1)) >> 3;
+    next = (uint32_t)(lo + (hi - lo) * r / per);
+    end = (uint32_t)(lo + (hi - lo) * (r + 1) / per);
+  }
+};
+
+// Segment a tile belongs to, cached in LDS by the tile loops below.
+struct SegCache {
+  uint32_t s, tb, tb_end, cb, seg0, logk;
+  uint64_t start, ubase;
+  uint32_t len, pad;
+};
+
+// Make sc describe the segment holding `tile` (reloading its splitter tree
+// into tk/ti) if the tile lies outside the cached segment.  Contains
+// __syncthreads(); called by every thread of the block.
+template <typename K, int THREADS>
+__device__ __forceinline__ void seg_for_tile(const Work& w, int cur, uint32_t m, uint32_t tile, SegCache& sc, K* tk,
+                                             uint32_t* ti, bool need_seg0) {
+  if (tile >= sc.tb && tile < sc.tb_end) return;  // uniform: sc is in LDS
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t s = find_seg(w.tile_base, m, tile);
+    const BigSeg bs = w.big[cur][s];
+    sc.s = s;
+    sc.tb = w.tile_base[s];
+    sc.tb_end = w.tile_base[s + 1];
+    sc.cb = w.count_base[s];
+    sc.seg0 = need_seg0 ? w.offsets[sc.cb] : 0u;
+    sc.logk = bs.logk;
+    sc.start = bs.start;
+    sc.ubase = bs.ubase;
+    sc.len = bs.len;
+  }
+  __syncthreads();
+  const K* tkey = (const K*)w.tree_key;
+  const uint32_t kk = 1u << sc.logk;
+  for (uint32_t i = threadIdx.x + 1; i < kk; i += THREADS) {
+    tk[i] = tkey[(uint64_t)sc.s * kMaxK + i];
+    ti[i] = w.tree_idx[(uint64_t)sc.s * kMaxK + i];
+  }
+  __syncthreads();
+}
+
 template <typename K, bool F32, bool SRC_IN, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_keys, int src_buf) {
   constexpr uint32_t TILE = THREADS * ITEMS;
   __shared__ K tk[kMaxK];
   __shared__ uint32_t ti[kMaxK];
   __shared__ uint32_t hist[kMaxK];
-  __shared__ uint32_t sh_s;
+  __shared__ SegCache sc;
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
   const uint32_t T = w.ctl->total_tiles;
   const K* bkey = SRC_IN ? nullptr : (const K*)w.buf_key[src_buf];
   const uint32_t* bidx = SRC_IN ? nullptr : w.buf_idx[src_buf];
-  const K* tkey = (const K*)w.tree_key;
-  for (uint32_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
-    if (threadIdx.x == 0) sh_s = find_seg(w.tile_base, m, tile);
-    __syncthreads();
-    const uint32_t s = sh_s;
-    const BigSeg bs = w.big[cur][s];
-    const uint32_t tl = tile - w.tile_base[s];
-    const uint32_t nt = w.tile_base[s + 1] - w.tile_base[s];
-    const uint32_t kk = 1u << bs.logk;
-    for (uint32_t i = threadIdx.x; i < kk; i += THREADS) {
-      hist[i] = 0;
-      if (i) {
-        tk[i] = tkey[(uint64_t)s * kMaxK + i];
-        ti[i] = w.tree_idx[(uint64_t)s * kMaxK + i];
-      }
-    }
-    __syncthreads();
-    const uint64_t base = bs.start + (uint64_t)tl * TILE;
-    const uint32_t cnt = min(TILE, bs.len - tl * TILE);
-#pragma unroll 4
+  const uint32_t lane = lane_id();
+  if (threadIdx.x == 0) {
+    sc.tb = 1;
+    sc.tb_end = 0;  // empty: forces a load
+  }
+  for (uint32_t i = threadIdx.x; i < kMaxK; i += THREADS) hist[i] = 0;
+  __syncthreads();
+  for (TileWalk tw(T); tw.next < tw.end; tw.next++) {
+    const uint32_t tile = tw.next;
+    seg_for_tile<K, THREADS>(w, cur, m, tile, sc, tk, ti, false);
+    const uint32_t tl = tile - sc.tb;
+    const uint64_t base = sc.start + (uint64_t)tl * TILE;
+    const uint32_t cnt = min(TILE, sc.len - tl * TILE);
+    K key[ITEMS];
+    bool valid[ITEMS];
+#pragma unroll
     for (int i = 0; i < ITEMS; i++) {
-      const uint32_t j = i * THREADS + threadIdx.x;
-      if (j < cnt) {
-        K key;
-        uint32_t idx;
-        if constexpr (SRC_IN) {
-          key = load_ord<K, F32>(in_keys, base + j);
-          idx = (uint32_t)(base + j - bs.ubase);
-        } else {
-          key = bkey[base + j];
-          idx = bidx[base + j];
-        }
-        atomicAdd(&hist[classify<K>(tk, ti, bs.logk, key, idx)], 1u);
+      const uint32_t jj = i * THREADS + threadIdx.x;
+      valid[i] = jj < cnt;
+      key[i] = K(0);
+      if (valid[i]) {
+        if constexpr (SRC_IN)
+          key[i] = load_ord<K, F32>(in_keys, base + jj);
+        else
+          key[i] = bkey[base + jj];
+      }
+    }
+    uint32_t b[ITEMS];
+    const uint64_t ub = sc.ubase;
+    classify_batch<K, ITEMS>(tk, ti, sc.logk, key, valid,
+                             [&](int i) -> uint32_t {
+                               const uint64_t pos = base + i * THREADS + threadIdx.x;
+                               if constexpr (SRC_IN)
+                                 return (uint32_t)(pos - ub);
+                               else
+                                 return bidx[pos];
+                             },
+                             b);
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      // one atomic per wave when the whole wave falls into one bucket
+      const uint64_t act = __ballot(valid[i]);
+      const uint32_t b0 = (uint32_t)__shfl(b[i], __ffsll((unsigned long long)act) - 1, kWave);
+      const uint64_t same = __ballot(valid[i] && b[i] == b0);
+      if (act && same == act) {
+        if (lane == (uint32_t)(__ffsll((unsigned long long)act) - 1)) atomicAdd(&hist[b0], (uint32_t)__popcll(act));
+      } else if (valid[i]) {
+        atomicAdd(&hist[b[i]], 1u);
       }
     }
     __syncthreads();
-    const uint32_t cb = w.count_base[s];
-    for (uint32_t b = threadIdx.x; b < kk; b += THREADS) w.counts[cb + b * nt + tl] = hist[b];
+    const uint32_t kk = 1u << sc.logk;
+    const uint32_t nt = sc.tb_end - sc.tb;
+    for (uint32_t bb = threadIdx.x; bb < kk; bb += THREADS) {
+      w.counts[sc.cb + bb * nt + tl] = hist[bb];
+      hist[bb] = 0;
+    }
     __syncthreads();
   }
 }
@@ -351,12 +468,13 @@ template <typename K, bool F32, bool SRC_IN, bool PAY, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* in_keys, const uint32_t* in_pay,
                                                      int src_buf, int dst_buf) {
   constexpr uint32_t TILE = THREADS * ITEMS;
+  static_assert(THREADS >= kMaxK, "one histogram bin per thread");
   __shared__ K tk[kMaxK];
   __shared__ uint32_t ti[kMaxK];
   __shared__ uint32_t hist[kMaxK];
   __shared__ uint64_t gdelta[kMaxK];
   __shared__ uint32_t tmp[THREADS / kWave + 1];
-  __shared__ uint32_t sh_s;
+  __shared__ SegCache sc;
   __shared__ K stage[TILE];
   __shared__ uint8_t stage_b[TILE];
   uint32_t* stage32 = reinterpret_cast<uint32_t*>(stage);
@@ -370,70 +488,91 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
   K* dkey = (K*)w.buf_key[dst_buf];
   uint32_t* didx = w.buf_idx[dst_buf];
   uint32_t* dpay = w.buf_pay[dst_buf];
-  const K* tkey = (const K*)w.tree_key;
+  const uint32_t lane = lane_id();
+  if (threadIdx.x == 0) {
+    sc.tb = 1;
+    sc.tb_end = 0;  // empty: forces a load
+  }
+  if (threadIdx.x < kMaxK) hist[threadIdx.x] = 0;
+  __syncthreads();
 
-  for (uint32_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
-    if (threadIdx.x == 0) sh_s = find_seg(w.tile_base, m, tile);
-    __syncthreads();
-    const uint32_t s = sh_s;
-    const BigSeg bs = w.big[cur][s];
-    const uint32_t tl = tile - w.tile_base[s];
-    const uint32_t nt = w.tile_base[s + 1] - w.tile_base[s];
-    const uint32_t kk = 1u << bs.logk;
-    const uint32_t cb = w.count_base[s];
-    const uint32_t seg0 = w.offsets[cb];
-    for (uint32_t i = threadIdx.x; i < kk; i += THREADS) {
-      hist[i] = 0;
-      if (i) {
-        tk[i] = tkey[(uint64_t)s * kMaxK + i];
-        ti[i] = w.tree_idx[(uint64_t)s * kMaxK + i];
-      }
-      gdelta[i] = bs.start + (uint64_t)(w.offsets[cb + i * nt + tl] - seg0);
-    }
-    __syncthreads();
+  for (TileWalk tw(T); tw.next < tw.end; tw.next++) {
+    const uint32_t tile = tw.next;
+    seg_for_tile<K, THREADS>(w, cur, m, tile, sc, tk, ti, true);
+    const uint32_t tl = tile - sc.tb;
+    const uint32_t nt = sc.tb_end - sc.tb;
+    const uint32_t kk = 1u << sc.logk;
+    // this tile's output offset of bucket threadIdx.x (loaded early, used after ranking)
+    uint64_t my_off = 0;
+    if (threadIdx.x < kk) my_off = sc.start + (uint64_t)(w.offsets[sc.cb + threadIdx.x * nt + tl] - sc.seg0);
+    const BigSeg bs{sc.start, sc.ubase, sc.len, sc.logk};
     const uint64_t base = bs.start + (uint64_t)tl * TILE;
     const uint32_t cnt = min(TILE, bs.len - tl * TILE);
     K key[ITEMS];
     uint32_t idx[ITEMS], pay[ITEMS], pos[ITEMS];
+    bool valid[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
-      const uint32_t j = i * THREADS + threadIdx.x;
-      pos[i] = 0xFFFFFFFFu;
-      if (j < cnt) {
+      const uint32_t jj = i * THREADS + threadIdx.x;
+      valid[i] = jj < cnt;
+      key[i] = K(0);
+      idx[i] = 0;
+      pay[i] = 0;
+      if (valid[i]) {
         if constexpr (SRC_IN) {
-          key[i] = load_ord<K, F32>(in_keys, base + j);
-          idx[i] = (uint32_t)(base + j - bs.ubase);
+          key[i] = load_ord<K, F32>(in_keys, base + jj);
+          idx[i] = (uint32_t)(base + jj - bs.ubase);
         } else {
-          key[i] = bkey[base + j];
-          idx[i] = bidx[base + j];
+          key[i] = bkey[base + jj];
+          idx[i] = bidx[base + jj];
         }
-        if constexpr (PAY) pay[i] = bpay[base + j];
-        const uint32_t b = classify<K>(tk, ti, bs.logk, key[i], idx[i]);
-        const uint32_t r = atomicAdd(&hist[b], 1u);
-        pos[i] = (b << 24) | r;  // r < TILE <= 2^24
+        if constexpr (PAY) pay[i] = bpay[base + jj];
       }
+    }
+    uint32_t b[ITEMS];
+    classify_batch<K, ITEMS>(tk, ti, bs.logk, key, valid, [&](int i) -> uint32_t { return idx[i]; }, b);
+    // rank inside (tile, bucket): one LDS atomic per element, or one per wave
+    // when the whole wave falls into a single bucket (skewed inputs)
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const uint64_t act = __ballot(valid[i]);
+      const uint32_t b0 = (uint32_t)__shfl(b[i], __ffsll((unsigned long long)act) - 1, kWave);
+      const uint64_t same = __ballot(valid[i] && b[i] == b0);
+      uint32_t r = 0;
+      if (act && same == act) {
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        uint32_t basev = 0;
+        if (lane == (uint32_t)leader) basev = atomicAdd(&hist[b0], (uint32_t)__popcll(act));
+        basev = __shfl(basev, leader, kWave);
+        r = basev + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
+      } else if (valid[i]) {
+        r = atomicAdd(&hist[b[i]], 1u);
+      }
+      pos[i] = valid[i] ? ((b[i] << 24) | r) : 0xFFFFFFFFu;  // r < TILE <= 2^24
     }
     __syncthreads();
     // exclusive scan of the tile histogram -> tile-local bucket starts
     {
-      static_assert(THREADS >= kMaxK, "one histogram bin per thread");
       const uint32_t hv = threadIdx.x < kk ? hist[threadIdx.x] : 0u;
       const uint32_t e = block_excl_scan<THREADS>(hv, tmp, nullptr);
-      if (threadIdx.x < kk) hist[threadIdx.x] = e;
-    }
-    __syncthreads();
-    for (uint32_t b = threadIdx.x; b < kk; b += THREADS) gdelta[b] -= hist[b];
-#pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      if (pos[i] != 0xFFFFFFFFu) {
-        const uint32_t b = pos[i] >> 24;
-        const uint32_t p = hist[b] + (pos[i] & 0xFFFFFFu);
-        pos[i] = p;
-        stage[p] = key[i];
-        stage_b[p] = (uint8_t)b;
+      if (threadIdx.x < kk) {
+        hist[threadIdx.x] = e;
+        gdelta[threadIdx.x] = my_off - e;
       }
     }
     __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      if (pos[i] != 0xFFFFFFFFu) {
+        const uint32_t bb = pos[i] >> 24;
+        const uint32_t p = hist[bb] + (pos[i] & 0xFFFFFFu);
+        pos[i] = p;
+        stage[p] = key[i];
+        stage_b[p] = (uint8_t)bb;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxK) hist[threadIdx.x] = 0;  // ready for the next tile
     for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) dkey[gdelta[stage_b[p]] + p] = stage[p];
     __syncthreads();
 #pragma unroll
@@ -620,7 +759,6 @@ static inline uint32_t grid_for(uint64_t work, uint32_t per_cu) {
 
 
 
-constexpr int kCntThreads = 256;
 constexpr int kSplThreads = 1024, kSplItems = 8;  // up to 8192 samples (a = 32, k = 256)
 
 // Algorithm of each size class: RFIS, RQuick or the LDS merge sort.
@@ -667,17 +805,19 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
       RS_LAUNCH((k_splitters<K, false, false, kSplThreads, kSplItems>), gs, kSplThreads, st, w, (int)lev, kin, src, a,
                 t.seed);
     }
-    const uint32_t gt = grid_for(tiles_max, 8);
+    // tiles: 256 threads x 16 keys (tile_log2 12) or 512 x 16 (tile_log2 13);
+    // the grid is a multiple of 8 for the XCD-aware tile walk
+    const uint32_t gt = std::max<uint32_t>(8u, grid_for(tiles_max, tile_log2 == 12 ? 8 : 4) & ~7u);
     if (tile_log2 == 12) {
       if (lev == 0)
-        RS_LAUNCH((k_count<K, F32, true, kCntThreads, 16>), gt, kCntThreads, st, w, (int)lev, kin, src);
+        RS_LAUNCH((k_count<K, F32, true, 256, 16>), gt, 256, st, w, (int)lev, kin, src);
       else
-        RS_LAUNCH((k_count<K, false, false, kCntThreads, 16>), gt, kCntThreads, st, w, (int)lev, kin, src);
+        RS_LAUNCH((k_count<K, false, false, 256, 16>), gt, 256, st, w, (int)lev, kin, src);
     } else {
       if (lev == 0)
-        RS_LAUNCH((k_count<K, F32, true, kCntThreads, 32>), gt, kCntThreads, st, w, (int)lev, kin, src);
+        RS_LAUNCH((k_count<K, F32, true, 512, 16>), gt, 512, st, w, (int)lev, kin, src);
       else
-        RS_LAUNCH((k_count<K, false, false, kCntThreads, 32>), gt, kCntThreads, st, w, (int)lev, kin, src);
+        RS_LAUNCH((k_count<K, false, false, 512, 16>), gt, 512, st, w, (int)lev, kin, src);
     }
     const uint32_t gsc = grid_for(w.count_max / kScanChunk + 1, 8);
     RS_LAUNCH(k_scan_reduce, gsc, kScanThreads, st, w);
@@ -685,16 +825,14 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
     RS_LAUNCH(k_scan_down, gsc, kScanThreads, st, w);
     if (tile_log2 == 12) {
       if (lev == 0)
-        RS_LAUNCH((k_scatter<K, F32, true, PAY, kCntThreads, 16>), gt, kCntThreads, st, w, (int)lev, kin, pay_in, src, dst);
+        RS_LAUNCH((k_scatter<K, F32, true, PAY, 256, 16>), gt, 256, st, w, (int)lev, kin, pay_in, src, dst);
       else
-        RS_LAUNCH((k_scatter<K, false, false, PAY, kCntThreads, 16>), gt, kCntThreads, st, w, (int)lev, kin, pay_in, src,
-                  dst);
+        RS_LAUNCH((k_scatter<K, false, false, PAY, 256, 16>), gt, 256, st, w, (int)lev, kin, pay_in, src, dst);
     } else {
       if (lev == 0)
-        RS_LAUNCH((k_scatter<K, F32, true, PAY, kCntThreads, 32>), gt, kCntThreads, st, w, (int)lev, kin, pay_in, src, dst);
+        RS_LAUNCH((k_scatter<K, F32, true, PAY, 512, 16>), gt, 512, st, w, (int)lev, kin, pay_in, src, dst);
       else
-        RS_LAUNCH((k_scatter<K, false, false, PAY, kCntThreads, 32>), gt, kCntThreads, st, w, (int)lev, kin, pay_in, src,
-                  dst);
+        RS_LAUNCH((k_scatter<K, false, false, PAY, 512, 16>), gt, 512, st, w, (int)lev, kin, pay_in, src, dst);
     }
     RS_LAUNCH(k_level_end, grid_for((w.big_max * kMaxK + 255) / 256, 4), 256, st, w, (int)lev, cap, target,
               last ? 1 : 0, (uint32_t)(dst + 1), ff);
