@@ -31,8 +31,8 @@
 namespace rs {
 
 // Size classes of final segments (upper bounds); the last is "oversize".
-__constant__ uint32_t c_class_max[kNumClasses] = {64, 256, 1024, 2048, 4096, 8192, 12288, 0xFFFFFFFFu};
-static const uint32_t h_class_max[kNumClasses] = {64, 256, 1024, 2048, 4096, 8192, 12288, 0xFFFFFFFFu};
+__constant__ uint32_t c_class_max[kNumClasses] = {64, 256, 1024, 2048, 3072, 4096, 6144, 8192, 12288, 0xFFFFFFFFu};
+static const uint32_t h_class_max[kNumClasses] = {64, 256, 1024, 2048, 3072, 4096, 6144, 8192, 12288, 0xFFFFFFFFu};
 
 __device__ __forceinline__ uint32_t class_of(uint32_t len, uint32_t cap, uint32_t force_fallback) {
   if (len > cap || (force_fallback && len > 64)) return kNumClasses - 1;

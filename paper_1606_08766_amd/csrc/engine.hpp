@@ -10,7 +10,7 @@ namespace rs {
 constexpr int kMaxLogK = 8;               // at most 256 buckets per level
 constexpr int kMaxK = 1 << kMaxLogK;
 constexpr int kMaxLevels = 8;
-constexpr int kNumClasses = 8;            // final-bucket size classes (see classes[] in engine.hip)
+constexpr int kNumClasses = 10;           // final-bucket size classes (see the class table in engine.hip)
 constexpr uint32_t kMaxOversample = 32;
 
 // A segment that the current level splits.

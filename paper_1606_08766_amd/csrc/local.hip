@@ -213,14 +213,22 @@ int launch_merge_class(int c, const Work& w, const K* kin, const uint32_t* pay_i
                 pay_out);
       break;
     case 4:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 512, 8>), grid_for(cap_c, 3), 512, st, w, c, kin, pay_in, kout, perm_out,
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 384, 8>), grid_for(cap_c, 4), 384, st, w, c, kin, pay_in, kout, perm_out,
                 pay_out);
       break;
     case 5:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 1024, 8>), grid_for(cap_c, 1), 1024, st, w, c, kin, pay_in, kout, perm_out,
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 512, 8>), grid_for(cap_c, 3), 512, st, w, c, kin, pay_in, kout, perm_out,
                 pay_out);
       break;
     case 6:
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 768, 8>), grid_for(cap_c, 2), 768, st, w, c, kin, pay_in, kout, perm_out,
+                pay_out);
+      break;
+    case 7:
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 1024, 8>), grid_for(cap_c, 1), 1024, st, w, c, kin, pay_in, kout, perm_out,
+                pay_out);
+      break;
+    case 8:
       if constexpr (!PAY) {
         RS_LAUNCH((k_local_sort<K, F32, PAY, 768, 16>), grid_for(cap_c, 1), 768, st, w, c, kin, pay_in, kout, perm_out,
                   pay_out);

@@ -421,6 +421,7 @@ int launch_rquick_class(int c, const Work& w, const K* kin, const uint32_t* pay_
       RS_LAUNCH((k_rquick<K, F32, PAY, 512, 2048, 16>), g, 512, st, w, c, kin, pay_in, kout, perm_out, pay_out, seed);
       break;
     case 4:
+    case 5:
       RS_LAUNCH((k_rquick<K, F32, PAY, 1024, 4096, 16>), g, 1024, st, w, c, kin, pay_in, kout, perm_out, pay_out, seed);
       break;
     default:
