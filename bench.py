@@ -54,6 +54,25 @@ def load_traffic():
     return t
 
 
+def kernel_key(name: str) -> str:
+    """Normalise a launch tag "(k_count<K, F32, true, 256, 16>)" or a profiler
+    name "rs::k_count<unsigned long, false, true, 256, 16>(rs::Work, ...)" to
+    "k_count/l1/256/16" (count/scatter carry their level) or
+    "k_local_sort/768/8"."""
+    import re
+
+    m = re.search(r"(k_[a-z_0-9]+)\s*<([^>]*)>", name)
+    if not m:
+        m2 = re.search(r"(k_[a-z_0-9]+)", name)
+        return m2.group(1) if m2 else name
+    base, args = m.group(1), [a.strip() for a in m.group(2).split(",")]
+    nums = [a for a in args if a.isdigit()]
+    parts = [base]
+    if base in ("k_count", "k_scatter", "k_splitters") and len(args) > 2:
+        parts.append("l1" if args[2] == "true" else "l2")
+    return "/".join(parts + nums)
+
+
 def kernel_class(name: str) -> str:
     """Map a launch tag to the pass it implements."""
     if "k_count" in name:
@@ -116,6 +135,15 @@ def bench_plain(args, R, torch):
     ko = torch.empty_like(inputs[0])
     po = torch.empty(n, dtype=torch.uint32, device="cuda")
     ws = torch.empty(R.plain_workspace_bytes(R.U64, n), dtype=torch.uint8, device="cuda")
+    if args.calib_copy_mib:
+        # a plain device copy of known size, so that profiler byte counters
+        # can be scaled by what they read for it
+        cb = args.calib_copy_mib << 20
+        src = torch.empty(cb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for s in range(args.warmup):
         R.sort(inputs[s % len(DISTS)], workspace=ws, out=(ko, po))
     torch.cuda.synchronize()
@@ -171,8 +199,8 @@ def bench_plain(args, R, torch):
         avg_s = dom_ms / dom_cnt / 1e3
         achieved = alg / avg_s / 1e9
         tr = None
-        if traffic and dom_name in traffic.get("kernels", {}):
-            tr = traffic["kernels"][dom_name]["bytes_per_launch"]
+        if traffic and kernel_key(dom_name) in traffic.get("kernels", {}):
+            tr = traffic["kernels"][kernel_key(dom_name)]["hbm_bytes_per_launch"]
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": dom_name,
                 "alg_bytes_per_launch": int(alg)}
@@ -201,8 +229,90 @@ def bench_plain(args, R, torch):
     return out
 
 
+def _read_pmc(path, counter):
+    """Per normalised kernel: (dispatches, mean counter value) from a rocprofv3
+    counter_collection.csv."""
+    import csv
+
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        k = kernel_key(r["Kernel_Name"]) if "rs::" in r["Kernel_Name"] else r["Kernel_Name"].split("(")[0]
+        d = acc.setdefault(k, {})
+        d[r["Dispatch_Id"]] = d.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    return {k: (len(v), sum(v.values()) / len(v)) for k, v in acc.items()}
+
+
+def pmc_summary(fetch_csv, write_csv, copy_mib, command, out_dir):
+    """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by what they read for a
+    plain copy of copy_mib MiB and write profiles/traffic.json + a text table."""
+    f = _read_pmc(fetch_csv, "FETCH_SIZE")
+    w = _read_pmc(write_csv, "WRITE_SIZE")
+    copy = [k for k in f if "copyBuffer" in k or "copy" in k.lower()]
+    if not copy:
+        raise SystemExit("no copy kernel found for calibration")
+    ck = max(copy, key=lambda k: f[k][1])
+    cb = copy_mib << 20
+    fr = cb / (f[ck][1] * 1024.0)
+    fw = cb / (w[ck][1] * 1024.0) if ck in w and w[ck][1] > 0 else 1.0
+    kern = {}
+    for k in sorted(set(f) | set(w)):
+        if not k.startswith("k_"):
+            continue
+        fb = f.get(k, (0, 0.0))[1] * 1024.0 * fr
+        wb = w.get(k, (0, 0.0))[1] * 1024.0 * fw
+        kern[k] = {"dispatches": f.get(k, w.get(k))[0], "fetch_bytes_per_launch": int(fb),
+                   "write_bytes_per_launch": int(wb), "hbm_bytes_per_launch": int(fb + wb)}
+    res = {"src_hash": src_hash(), "command": command,
+           "calibration": {"copy_kernel": ck, "copy_bytes": cb, "fetch_kib": f[ck][1],
+                           "write_kib": w.get(ck, (0, 0))[1], "fetch_scale": fr, "write_scale": fw},
+           "kernels": kern}
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, "traffic.json"), "w") as fh:
+        json.dump(res, fh, indent=1)
+    lines = ["HBM traffic per kernel launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (two separate runs),",
+             "scaled by the counters of a plain %d MiB device copy (%s): read x%.3f, write x%.3f." % (
+                 copy_mib, ck, fr, fw),
+             "command: " + command, "source hash: " + res["src_hash"], "",
+             "%-28s %10s %14s %14s %14s" % ("kernel", "dispatches", "fetch MB", "write MB", "total MB")]
+    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["hbm_bytes_per_launch"]):
+        lines.append("%-28s %10d %14.2f %14.2f %14.2f" % (k, v["dispatches"], v["fetch_bytes_per_launch"] / 1e6,
+                                                          v["write_bytes_per_launch"] / 1e6,
+                                                          v["hbm_bytes_per_launch"] / 1e6))
+    with open(os.path.join(out_dir, "hbm_traffic_plain_2p28_u64.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def trace_summary(stats_csv, command, out_path, title):
+    """Short text table from a rocprofv3 --stats kernel_stats.csv."""
+    import csv
+
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [title, "command: " + command, "source hash: " + src_hash(), "",
+             "%-34s %7s %12s %12s %7s" % ("kernel", "calls", "total ms", "avg us", "%")]
+    for r in rows:
+        nm = r.get("Name") or r.get("KernelName") or ""
+        key = kernel_key(nm) if "rs::" in nm else nm[:34]
+        lines.append("%-34s %7s %12.3f %12.1f %7.2f" % (key[:34], r.get("Calls"), float(r.get("TotalDurationNs", 0)) / 1e6,
+                                                       float(r.get("AverageNs", 0)) / 1e3,
+                                                       float(r.get("Percentage", 0))))
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run a plain device copy of this size before timing (profiler calibration)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 --pmc runs into profiles/ (no GPU needed)")
+    ap.add_argument("--trace-summary", metavar="KERNEL_STATS_CSV",
+                    help="summarise a rocprofv3 --stats run into profiles/ (no GPU needed)")
+    ap.add_argument("--profile-command", default="", help="command recorded in the summaries")
+    ap.add_argument("--profile-name", default="kernel_trace_plain_2p28_u64.txt")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=5)
@@ -210,6 +320,14 @@ def main():
     ap.add_argument("--workload", default="plain", choices=["plain", "batched", "small", "serving"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.calib_copy_mib or 1024, args.profile_command,
+                    os.path.join(ROOT, "profiles"))
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.profile_command, os.path.join(ROOT, "profiles", args.profile_name),
+                      "rocprofv3 --kernel-trace --stats summary")
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this sort's multi-GPU path is a design, not a build "
               "(see DESIGN.md); run with --gpus 1", file=sys.stderr)

@@ -17,7 +17,7 @@ struct Tuning {
   uint32_t rfis_max = 256;    // classes with upper bound <= rfis_max use RFIS
   uint32_t rquick_max = 1;    // classes with upper bound <= rquick_max use RQuick
   uint64_t seed = 0x5EED5EED12345678ull;
-  uint32_t tile_log2 = 13;
+  uint32_t tile_log2 = 12;
   uint32_t force_fallback = 0;
 };
 
