@@ -19,6 +19,7 @@ sort server, p50/p99 latency).
 from __future__ import annotations
 
 import argparse
+import collections
 import hashlib
 import json
 import os
@@ -191,10 +192,27 @@ def bench_plain(args, R, torch):
     if dom_class in bpk:
         # launches of this kernel per sort, and the keys one launch processes
         launches_per_sort = dom_cnt / args.steps
-        keys_per_launch = n / launches_per_sort if dom_class != "local_sort" else None
-        if keys_per_launch is None:
-            # a local-sort class kernel processes the keys of its size class
-            keys_per_launch = n * (dom_ms / agg["local_sort"]["ms"]) / launches_per_sort
+        if dom_class != "local_sort":
+            keys_per_launch = n / launches_per_sort
+        else:
+            # a local-sort kernel sorts the keys of one size class: exact count
+            # per distribution from the device statistics, averaged over the mix
+            import re
+
+            nums = [int(v) for v in re.findall(r"\b(\d+)\b", dom_name)]
+            if "k_rfis" in dom_name:
+                caps = {nums[-1]}
+            elif "k_rquick" in dom_name:
+                caps = {nums[-2]} if nums[-2] <= 2048 else {3072, 4096}
+            else:
+                caps = {nums[-2] * nums[-1]}
+            ks_sum = 0
+            for s in range(args.steps):
+                R.sort(inputs[s % len(DISTS)], workspace=ws, out=(ko, po))
+                for cmax, _, keys in R.class_stats(ws):
+                    if cmax in caps:
+                        ks_sum += keys
+            keys_per_launch = ks_sum / args.steps / launches_per_sort
         alg = bpk[dom_class] * keys_per_launch
         avg_s = dom_ms / dom_cnt / 1e3
         achieved = alg / avg_s / 1e9
@@ -227,6 +245,225 @@ def bench_plain(args, R, torch):
         "hbm_bytes_per_key_algorithmic": sum(bpk.values()),
     }
     return out
+
+
+def _timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def bench_batched(args, R, torch):
+    """Config 4: 100k segments with log-uniform sizes, u64 keys + u32 payload,
+    Uniform / Zero / DeterDupl per segment.  One rsort_segmented call against
+    rsort_plain per segment (keys + perm only, back to back on one stream)."""
+    from gen import gen
+
+    count = 100_000
+    hi = 18 if args.batched_variant == "literal" else 13
+    sizes = gen.log_uniform_sizes(count, 0, hi, seed=1)
+    dists = gen.pick_dists(count, ["uniform", "zero", "deterdupl"], seed=2)
+    keys, pay, off = gen.segmented("u64", sizes, dists, seed=3)
+    n = keys.size
+    dk, dp, do = torch.from_numpy(keys).cuda(), torch.from_numpy(pay).cuda(), torch.from_numpy(off).cuda()
+    del keys, pay
+    ko, po, plo = torch.empty_like(dk), torch.empty(n, dtype=torch.uint32, device="cuda"), torch.empty_like(dp)
+    ws = torch.empty(R.segmented_workspace_bytes(R.U64, n, count, True), dtype=torch.uint8, device="cuda")
+    R.timing_begin()
+    t_b = _timed(torch, lambda: R.segmented_sort(dk, do, dp, workspace=ws, out=(ko, po, plo)), args.steps, args.warmup)
+    timing = R.timing_end()
+    if R.workspace_status(ws) != 0:
+        raise RuntimeError("segmented sort reported an error")
+    # plain baseline on the first segments (enough for a stable rate)
+    m = 4000
+    offh = off[:m + 1]
+    npl = int(offh[-1])
+    wsp = torch.empty(max(R.plain_workspace_bytes(R.U64, int(sizes[:m].max())), 256), dtype=torch.uint8,
+                      device="cuda")
+
+    def plain_loop():
+        for s in range(m):
+            a, b = int(offh[s]), int(offh[s + 1])
+            if b > a:
+                R.sort(dk[a:b], workspace=wsp, out=(ko[a:b], po[a:b]))
+
+    t_p = _timed(torch, plain_loop, 1, 1)
+    batched = n / t_b / 1e9
+    plain = npl / t_p / 1e9
+    per = {}
+    calls = args.steps + args.warmup  # the event log spans the warmup calls too
+    for name, (cnt, ms) in timing.items():
+        c = kernel_class(name)
+        per[c] = round(per.get(c, 0.0) + ms / calls, 4)
+    return {
+        "metric": "Gkeys/s (batched segmented sort, %d segments)" % count,
+        "value": round(batched, 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_b * 1e3, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "100k segments, sizes log-uniform in [1, 2^%d], u64 keys + u32 payload, "
+                               "Uniform/Zero/DeterDupl per segment" % hi, "n": n, "segments": count},
+        "plain_per_segment_gkeys_s": round(plain, 3), "batched_over_plain": round(batched / plain, 2),
+        "plain_sample": "rsort_plain on the first %d segments (%d keys), keys + perm only" % (m, npl),
+        "ms_per_pass": per,
+    }
+
+
+def bench_small(args, R, torch):
+    """Config 3: 2^14 independent arrays of n in {64, 256, 1024, 4096} u32 keys
+    (uniform, 8 distinct values) by RFIS, RQuick and the LDS merge sort."""
+    from gen import gen
+
+    arrays = 1 << 14
+    rows = []
+    algos = {"rfis": dict(rfis_max=1024, rquick_max=1), "rquick": dict(rfis_max=1, rquick_max=4096),
+             "merge": dict(rfis_max=1, rquick_max=1)}
+    for n in (64, 256, 1024, 4096):
+        for dist in ("uniform", "dup8"):
+            x = gen.keys("u32", "uniform" if dist == "uniform" else "topbits", arrays * n, seed=1,
+                         param=0 if dist == "uniform" else 3)
+            off = torch.arange(0, arrays * n + 1, n, dtype=torch.int64).cuda()
+            dx = torch.from_numpy(x).cuda()
+            ko, po = torch.empty_like(dx), torch.empty(dx.numel(), dtype=torch.uint32, device="cuda")
+            ws = torch.empty(R.segmented_workspace_bytes(R.U32, dx.numel(), arrays, False), dtype=torch.uint8,
+                             device="cuda")
+            for a, tune in algos.items():
+                if a == "rfis" and n > 1024:
+                    continue
+                if a == "rquick" and n < 2048:
+                    continue
+                with R.tuned(**tune):
+                    t = _timed(torch, lambda: R.segmented_sort(dx, off, workspace=ws, out=(ko, po, None)), args.steps,
+                               args.warmup)
+                row = {"n": n, "dist": dist, "algo": a, "ms": round(t * 1e3, 4), "arrays_per_s": round(arrays / t),
+                       "gkeys_s": round(arrays * n / t / 1e9, 3)}
+                if a == "rfis":
+                    row["compares_per_s"] = float("%.4g" % (arrays * n * n / t))
+                rows.append(row)
+    best = max(r["gkeys_s"] for r in rows if r["n"] == 4096)
+    return {"metric": "Gkeys/s (2^14 small arrays, best algorithm at n = 4096)", "value": best, "unit": "Gkeys/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "2^14 arrays x n in {64, 256, 1024, 4096}, u32 uniform / 8 distinct values"},
+            "rows": rows}
+
+
+def bench_serving(args, R, torch):
+    """Config 5: Poisson stream of sort requests through the sort server at
+    0.5x and 0.8x of its measured closed-loop rate; sizes log-uniform in
+    [2^8, 2^26], key type and distribution drawn per request; 64 GiB budget."""
+    import numpy as np
+
+    from gen import gen
+
+    pool_n = 1 << 26
+    kts = [("u32", R.U32), ("u64", R.U64), ("f32", R.F32)]
+    pool = {}
+    for kname, kt in kts:
+        for d in DISTS:
+            pool[(kname, d)] = torch.from_numpy(gen.keys(kname, d, pool_n, seed=5)).cuda()
+    rng = np.random.default_rng(1)
+    total = args.requests + args.serve_warmup
+    sizes = np.floor(2.0 ** rng.uniform(8, 26, total)).astype(np.int64)
+    kinds = [(kts[rng.integers(3)], DISTS[rng.integers(5)]) for _ in range(total)]
+    offs = [int(rng.integers(0, pool_n - s + 1)) for s in sizes]
+    # every request writes to its own region of one output arena, so the
+    # client never waits for a buffer: latency is the server's alone
+    # output ring of 2^32 keys (+ perm): a request takes the next region that
+    # no pending request holds (regions are freed oldest first), so a client
+    # waits for a buffer only when 2^32 keys are pending
+    ring = 1 << 32
+    arena_k = torch.empty(ring, dtype=torch.uint64, device="cuda")
+    arena_p = torch.empty(ring, dtype=torch.uint32, device="cuda")
+    budget = 64 << 30
+    inflight = 16
+
+    def run(qps):
+        lat, keys, starts, ends = [], 0, [], []
+        live = collections.OrderedDict()  # ticket -> region start, in allocation order
+        head = 0
+
+        def place(n):
+            lo = next(iter(live.values())) if live else None
+            for pos in ((head,) if head + n <= ring else ()) + (0,):
+                if pos + n > ring:
+                    continue
+                if lo is None or (lo < head and (pos >= head or pos + n <= lo)) or (head <= lo and pos >= head
+                                                                                  and pos + n <= lo):
+                    return pos
+            return None
+
+        with R.Server(device=0, hbm_budget_bytes=budget, max_inflight=inflight) as s:
+            t0 = time.monotonic_ns()
+            gaps = rng.exponential(1.0 / qps, total) if qps else np.zeros(total)
+            arrive = t0 + np.cumsum(gaps * 1e9).astype(np.int64)
+            pending = {}
+            i = 0
+            while i < total or pending:
+                now = time.monotonic_ns()
+                while i < total and arrive[i] <= now:
+                    (kname, kt), d = kinds[i]
+                    src = pool[(kname, d)]
+                    n = int(sizes[i])
+                    pos = place(n)
+                    if pos is None:
+                        break
+                    tk = s.submit(kt, src.data_ptr() + offs[i] * src.element_size(), n,
+                                  arena_k.data_ptr() + 8 * pos, arena_p.data_ptr() + 4 * pos)
+                    live[tk] = pos
+                    head = pos + n
+                    pending[tk] = (i, int(arrive[i]))
+                    i += 1
+                done = []
+                for tk, (j, arr) in pending.items():
+                    rc, r = s.poll(tk)
+                    if rc != R.PENDING:
+                        if rc != R.OK:
+                            raise RuntimeError("request failed: %d" % rc)
+                        done.append(tk)
+                        if j >= args.serve_warmup:
+                            lat.append((r.t_done_ns - arr) / 1e6)
+                            keys += int(sizes[j])
+                            starts.append(r.t_start_ns)
+                            ends.append(r.t_done_ns)
+                for tk in done:
+                    del pending[tk]
+                    del live[tk]
+                    s.release(tk)
+                if not done:
+                    time.sleep(20e-6)
+        span = (max(ends) - min(starts)) / 1e9
+        # busy fraction: share of the span with at least one request on the GPU
+        busy, cur_s, cur_e = 0, None, None
+        for a, b in sorted(zip(starts, ends)):
+            if cur_e is None or a > cur_e:
+                if cur_e is not None:
+                    busy += cur_e - cur_s
+                cur_s, cur_e = a, b
+            else:
+                cur_e = max(cur_e, b)
+        busy += cur_e - cur_s
+        lat = np.array(lat)
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "gkeys_s": round(keys / span / 1e9, 3), "requests": int(lat.size),
+                "gpu_busy_frac": round(busy / 1e9 / span, 3)}
+
+    closed = run(0)  # all requests released at once: closed-loop saturation
+    sat_qps = closed["requests"] / ((closed["requests"] * np.mean(sizes)) / (closed["gkeys_s"] * 1e9))
+    res = {"closed_loop": closed, "saturation_qps": round(float(sat_qps), 1)}
+    for f in (0.5, 0.8):
+        res["qps_%.1fx" % f] = dict(run(f * sat_qps), qps=round(float(f * sat_qps), 1))
+    return {"metric": "p50/p99 sort-request latency (ms) at 0.5x / 0.8x saturation QPS",
+            "value": res["qps_0.8x"]["p99_ms"], "unit": "ms (p99 at 0.8x saturation)", "n_gpus": 1,
+            "steps": total, "warmup": args.serve_warmup, "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32/u64/f32", "data": "synthetic",
+            "config": {"workload": "Poisson sort requests, sizes log-uniform [2^8, 2^26], key type uniform over "
+                                   "u32/u64/f32, 5 distributions, 64 GiB budget, %d streams" % inflight},
+            "serving": res}
 
 
 def _read_pmc(path, counter):
@@ -319,6 +556,9 @@ def main():
     ap.add_argument("--n-log2", type=int, default=28)
     ap.add_argument("--workload", default="plain", choices=["plain", "batched", "small", "serving"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-variant", default="1gib", choices=["1gib", "literal"])
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.calib_copy_mib or 1024, args.profile_command,
@@ -338,11 +578,13 @@ def main():
 
     if args.workload == "plain":
         out = bench_plain(args, R, torch)
+    elif args.workload == "batched":
+        out = bench_batched(args, R, torch)
+    elif args.workload == "small":
+        out = bench_small(args, R, torch)
     else:
-        from paper_1606_08766_amd import workloads
-
-        out = workloads.run(args.workload, args, R, torch)
-    if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
+        out = bench_serving(args, R, torch)
+    if args.workload == "plain" and not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         out["cpu_baseline"] = cpu_baseline(args.n_log2)
     print(json.dumps(out), flush=True)
 

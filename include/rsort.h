@@ -122,6 +122,14 @@ int rsort_stats(const void *workspace, void *stream, uint64_t *spl_keys, uint32_
                 uint32_t *bucket_sizes, uint32_t *num_buckets, uint32_t *levels,
                 uint32_t *level_max, uint32_t *level_buckets, uint32_t *oversize);
 
+/* Size classes of the final buckets of the last call that used `workspace`
+ * (synchronises stream).  For up to max_classes classes: the largest bucket
+ * the class sorts (0xFFFFFFFF for the global-memory fallback class), the
+ * number of buckets and the number of keys routed to it.  Any output may be
+ * NULL.  Returns the number of classes (>= 0) or an error. */
+int rsort_class_stats(const void *workspace, void *stream, uint32_t max_classes,
+                      uint32_t *class_max, uint32_t *buckets, uint64_t *keys);
+
 /* ------------------------------------------------------------------------
  * Tuning.  Fields set to 0 keep their current value.  Applies to calls made
  * after it returns (process-wide, not thread-safe against concurrent calls).
@@ -143,16 +151,26 @@ int rsort_get_tuning(rsort_tuning *out);
 int rsort_set_tuning(const rsort_tuning *in);
 
 /* ------------------------------------------------------------------------
- * Sort server (continuous batching).  Requests are admitted while the sum of
- * their footprints (input + output + workspace bytes) fits hbm_budget_bytes
- * and fewer than max_inflight are on the device; admitted requests run on a
- * pool of HIP streams so their work overlaps on the device.  Small requests
- * of the same key type admitted together are sorted by one segmented launch.
+ * Sort server (continuous batching).  At creation the server reserves
+ * hbm_budget_bytes of device memory as its scratch arena and creates
+ * max_inflight HIP streams (slots).  Every in-flight sort takes its scratch
+ * (workspace, and for packed batches the packed buffers) from the arena and
+ * returns it on completion; no device memory is allocated while serving.
+ *
+ * Requests of more than 2^20 keys are admitted in arrival order, one per
+ * slot, when their scratch fits the arena.  Smaller requests are queued and
+ * packed: whenever a small-request slot is free (at most two batches in
+ * flight), the queued small requests of the oldest one's key type (up to 1024
+ * requests and 2^24 keys, within the arena's largest free block) are sorted
+ * by one segmented sort between one gather and one scatter-back launch.  A
+ * request's result is bit-identical to the one it gets alone.  A device
+ * error in a packed batch is reported to every request of that batch.
  *
  * Request buffers are device pointers owned by the caller and must stay
- * valid until rsort_poll returns something other than RSORT_PENDING.  The
- * server owns its workspace memory (allocated once per worker slot and
- * charged to the budget).
+ * valid until rsort_poll returns something other than RSORT_PENDING.
+ * Setting the environment variable RSORT_SERVER_LOG to a file path makes
+ * each server append one line per launch (slot, requests, keys, host
+ * enqueue time) and per completion to that file.
  * ---------------------------------------------------------------------- */
 typedef struct rsort_server rsort_server;
 
@@ -172,7 +190,13 @@ typedef struct {
   uint32_t batch_size;  /* requests sorted in the same launch */
 } rsort_result;
 
-/* device: HIP device ordinal.  max_inflight: concurrent requests (>= 1). */
+/* Arena bytes one request of n keys takes when it runs alone (0 for n == 0
+ * or a bad key type).  Requests above hbm_budget_bytes get RSORT_ENOMEM. */
+size_t rsort_server_request_bytes(rsort_key_t kt, uint64_t n);
+/* device: HIP device ordinal, or < 0 for a host-only fake executor (tests of
+ * the scheduling logic: no GPU, buffers untouched).  max_inflight: slots
+ * (1..64); with two or more, slot 0 serves only requests of at most 2^20 keys.
+ * RSORT_ENOMEM if the arena cannot be allocated. */
 int rsort_server_create(int device, uint64_t hbm_budget_bytes, uint32_t max_inflight,
                         rsort_server **out);
 /* Waits for every admitted request, then frees server memory. */
@@ -188,7 +212,7 @@ int rsort_poll(rsort_server *s, uint64_t ticket, rsort_result *out);
 int rsort_wait(rsort_server *s, uint64_t ticket, uint32_t timeout_ms, rsort_result *out);
 /* Forget a finished ticket. */
 int rsort_release(rsort_server *s, uint64_t ticket);
-/* Counters: requests queued, running, finished; bytes in use. */
+/* Counters: requests queued, running, finished; arena bytes in use. */
 int rsort_server_counters(rsort_server *s, uint64_t *queued, uint64_t *running,
                           uint64_t *finished, uint64_t *bytes_in_use);
 

@@ -139,6 +139,21 @@ int rsort_stats(const void* workspace, void* stream, uint64_t* spl_keys, uint32_
   return c.status;
 }
 
+int rsort_class_stats(const void* workspace, void* stream, uint32_t max_classes, uint32_t* class_max,
+                      uint32_t* buckets, uint64_t* keys) {
+  if (!workspace) return RSORT_EINVAL;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return RSORT_EDEVICE;
+  rs::Ctl c;
+  if (hipMemcpy(&c, workspace, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) return RSORT_EDEVICE;
+  const uint32_t m = std::min<uint32_t>(max_classes, rs::kNumClasses);
+  for (uint32_t i = 0; i < m; i++) {
+    if (class_max) class_max[i] = rs::class_max((int)i);
+    if (buckets) buckets[i] = c.class_count[i];
+    if (keys) keys[i] = c.class_keys[i];
+  }
+  return (int)rs::kNumClasses;
+}
+
 int rsort_get_tuning(rsort_tuning* out) {
   if (!out) return RSORT_EINVAL;
   const rs::Tuning& t = rs::tuning();

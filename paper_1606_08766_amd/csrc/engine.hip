@@ -34,6 +34,8 @@ namespace rs {
 __constant__ uint32_t c_class_max[kNumClasses] = {64, 256, 1024, 2048, 3072, 4096, 6144, 8192, 12288, 0xFFFFFFFFu};
 static const uint32_t h_class_max[kNumClasses] = {64, 256, 1024, 2048, 3072, 4096, 6144, 8192, 12288, 0xFFFFFFFFu};
 
+uint32_t class_max(int c) { return (c >= 0 && c < kNumClasses) ? h_class_max[c] : 0u; }
+
 __device__ __forceinline__ uint32_t class_of(uint32_t len, uint32_t cap, uint32_t force_fallback) {
   if (len > cap || (force_fallback && len > 64)) return kNumClasses - 1;
   uint32_t c = 0;
@@ -70,6 +72,17 @@ __device__ __forceinline__ void route(const Work& w, uint32_t* big_counter, BigS
       w.cls[c][j] = FinalSeg{start, len, src};
     else
       set_status(w.ctl, -3);
+  }
+  // keys per class (statistics): one 64-bit atomic per distinct class per wave
+  uint64_t pending = __ballot(af);
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t k = __shfl(c, leader, kWave);
+    const bool mine = af && c == k;
+    uint64_t sum = mine ? (uint64_t)len : 0ull;
+    for (int d = kWave / 2; d > 0; d >>= 1) sum += __shfl_xor(sum, d, kWave);
+    if (lane_id() == (uint32_t)leader) atomicAdd((unsigned long long*)&w.ctl->class_keys[k], (unsigned long long)sum);
+    pending &= ~__ballot(mine);
   }
 }
 
@@ -765,8 +778,10 @@ constexpr int kSplThreads = 1024, kSplItems = 8;  // up to 8192 samples (a = 32,
 template <typename K, bool F32, bool PAY>
 static int launch_class_sort(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
                              uint32_t* pay_out, uint64_t cap_c, hipStream_t st, const Tuning& t) {
-  if (h_class_max[c] <= t.rfis_max) return launch_rfis_class<K, F32, PAY>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, st);
-  if (h_class_max[c] <= t.rquick_max)
+  const int cb = c & 0xFF;  // c may carry kDirect
+  if (h_class_max[cb] <= t.rfis_max)
+    return launch_rfis_class<K, F32, PAY>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, st);
+  if (h_class_max[cb] <= t.rquick_max)
     return launch_rquick_class<K, F32, PAY>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, st);
   return launch_merge_class<K, F32, PAY>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, st);
 }
@@ -787,6 +802,12 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
   const K* kin = (const K*)keys_in;
   K* kout = (K*)keys_out;
 
+  if (!seg_off && levels == 0 && !ff && n <= cap) {
+    // the whole input fits one workgroup: one launch, no segment lists
+    int c = 0;
+    while (n > h_class_max[c]) c++;
+    return launch_class_sort<K, F32, PAY>(c | kDirect, w, kin, pay_in, kout, perm_out, pay_out, 1, st, t);
+  }
   RS_LAUNCH(k_reset, 1, 256, st, w.ctl, levels);
   RS_LAUNCH(k_init, grid_for((num_segs + 255) / 256, 4), 256, st, w, seg_off, num_segs, n, cap, target, levels, ff);
 

@@ -38,6 +38,7 @@ struct Ctl {
   uint32_t class_count[kNumClasses];  // final segments per size class (last = oversize)
   uint32_t level_max[kMaxLevels];  // largest bucket created per level
   uint32_t level_buckets[kMaxLevels];
+  uint64_t class_keys[kNumClasses];  // keys routed to each size class
   // diagnostics of level 0, segment 0
   uint32_t l0_k;
   uint32_t pad0;
@@ -64,5 +65,33 @@ struct Work {
   uint32_t* buf_pay[2];  // [n] (payload calls only)
   uint64_t big_max, count_max, scan_blocks, n;
 };
+
+// Launcher flag (or-ed into the class index): sort the whole input of a
+// plain call as one segment in a single launch.  The kernels then receive a
+// negative class argument.
+constexpr int kDirect = 0x100;
+
+// Final segments of class cls (cls < 0: the direct single-segment mode).
+__device__ __forceinline__ uint32_t final_count(const Work& w, int cls) {
+  if (cls < 0) return 1u;
+  return (uint32_t)min((uint64_t)w.ctl->class_count[cls], w.cls_cap[cls]);
+}
+__device__ __forceinline__ FinalSeg final_at(const Work& w, int cls, uint32_t q) {
+  if (cls < 0) return FinalSeg{0ull, (uint32_t)w.n, 0u};
+  return w.cls[cls][q];
+}
+// In the direct mode no reset kernel runs: the first thread clears the status
+// and statistics of the workspace.
+__device__ __forceinline__ void direct_reset(const Work& w, int cls) {
+  if (cls < 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+    w.ctl->status = 0;
+    w.ctl->levels = 0;
+    w.ctl->l0_k = 0;
+    for (int c = 0; c < kNumClasses; c++) {
+      w.ctl->class_count[c] = 0;
+      w.ctl->class_keys[c] = 0;
+    }
+  }
+}
 
 }  // namespace rs

@@ -53,7 +53,21 @@ int enqueue_median_tree(const uint64_t* vals, uint64_t per_problem, const uint64
                         uint32_t k, const uint8_t* coins, uint32_t num_problems, uint64_t* out, void* ws,
                         size_t ws_bytes, hipStream_t st);
 
+// One request of a packed batch (sort server): source keys, destination
+// keys / permutation, length and offset inside the packed arrays.
+struct BatchEntry {
+  const void* src;
+  void* dst_keys;
+  uint32_t* dst_perm;
+  uint64_t n;
+  uint64_t off;
+};
+int enqueue_batch_in(const BatchEntry* tab_dev, uint32_t count, uint32_t key_bytes, void* packed, hipStream_t st);
+int enqueue_batch_out(const BatchEntry* tab_dev, uint32_t count, uint32_t key_bytes, const void* keys,
+                      const uint32_t* perm, hipStream_t st);
+
 uint32_t num_cu_cached();
+uint32_t class_max(int c);  // upper bound of final-bucket size class c
 
 }  // namespace rs
 

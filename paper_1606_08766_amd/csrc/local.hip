@@ -29,10 +29,10 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
   __shared__ uint32_t s_v[NP];
   __shared__ uint32_t s_p[PAY ? NP : 1];
   const LdsArr<K> sa{s_lo, s_hi, s_v, s_p};
-  const uint32_t cnt = w.ctl->class_count[cls];
-  const uint32_t cnt_c = (uint32_t)min((uint64_t)cnt, w.cls_cap[cls]);
+  direct_reset(w, cls);
+  const uint32_t cnt_c = final_count(w, cls);
   for (uint32_t q = blockIdx.x; q < cnt_c; q += gridDim.x) {
-    const FinalSeg f = w.cls[cls][q];
+    const FinalSeg f = final_at(w, cls, q);
     const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
     const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
     const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
@@ -197,40 +197,42 @@ __global__ __launch_bounds__(THREADS) void k_oversize(Work w, const K* in_keys, 
 template <typename K, bool F32, bool PAY>
 int launch_merge_class(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
                        uint32_t* pay_out, uint64_t cap_c, hipStream_t st) {
-  switch (c) {
+  const int ca = (c & kDirect) ? -1 : c;  // kernel class argument
+  auto gfc = [&](uint64_t cc, uint32_t per) { return (c & kDirect) ? 1u : grid_for(cc, per); };
+  switch (c & 0xFF) {
     case 0:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 64, 1>), grid_for(cap_c, 16), 64, st, w, c, kin, pay_in, kout, perm_out, pay_out);
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 64, 1>), gfc(cap_c, 16), 64, st, w, ca, kin, pay_in, kout, perm_out, pay_out);
       break;
     case 1:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 64, 4>), grid_for(cap_c, 16), 64, st, w, c, kin, pay_in, kout, perm_out, pay_out);
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 64, 4>), gfc(cap_c, 16), 64, st, w, ca, kin, pay_in, kout, perm_out, pay_out);
       break;
     case 2:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 256, 4>), grid_for(cap_c, 8), 256, st, w, c, kin, pay_in, kout, perm_out,
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 256, 4>), gfc(cap_c, 8), 256, st, w, ca, kin, pay_in, kout, perm_out,
                 pay_out);
       break;
     case 3:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 256, 8>), grid_for(cap_c, 8), 256, st, w, c, kin, pay_in, kout, perm_out,
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 256, 8>), gfc(cap_c, 8), 256, st, w, ca, kin, pay_in, kout, perm_out,
                 pay_out);
       break;
     case 4:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 384, 8>), grid_for(cap_c, 4), 384, st, w, c, kin, pay_in, kout, perm_out,
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 384, 8>), gfc(cap_c, 4), 384, st, w, ca, kin, pay_in, kout, perm_out,
                 pay_out);
       break;
     case 5:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 512, 8>), grid_for(cap_c, 3), 512, st, w, c, kin, pay_in, kout, perm_out,
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 512, 8>), gfc(cap_c, 3), 512, st, w, ca, kin, pay_in, kout, perm_out,
                 pay_out);
       break;
     case 6:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 768, 8>), grid_for(cap_c, 2), 768, st, w, c, kin, pay_in, kout, perm_out,
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 768, 8>), gfc(cap_c, 2), 768, st, w, ca, kin, pay_in, kout, perm_out,
                 pay_out);
       break;
     case 7:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 1024, 8>), grid_for(cap_c, 1), 1024, st, w, c, kin, pay_in, kout, perm_out,
+      RS_LAUNCH((k_local_sort<K, F32, PAY, 1024, 8>), gfc(cap_c, 1), 1024, st, w, ca, kin, pay_in, kout, perm_out,
                 pay_out);
       break;
     case 8:
       if constexpr (!PAY) {
-        RS_LAUNCH((k_local_sort<K, F32, PAY, 768, 16>), grid_for(cap_c, 1), 768, st, w, c, kin, pay_in, kout, perm_out,
+        RS_LAUNCH((k_local_sort<K, F32, PAY, 768, 16>), gfc(cap_c, 1), 768, st, w, ca, kin, pay_in, kout, perm_out,
                   pay_out);
       }
       break;

@@ -62,9 +62,10 @@ __global__ __launch_bounds__(THREADS) void k_rfis(Work w, int cls, const K* in_k
   constexpr int PER = (NMAX + THREADS - 1) / THREADS;
   __shared__ T sx[NMAX];
   __shared__ uint16_t dest[NMAX];  // dest[rank] = local index of that element
-  const uint32_t cnt = (uint32_t)min((uint64_t)w.ctl->class_count[cls], w.cls_cap[cls]);
+  direct_reset(w, cls);
+  const uint32_t cnt = final_count(w, cls);
   for (uint32_t q = blockIdx.x; q < cnt; q += gridDim.x) {
-    const FinalSeg f = w.cls[cls][q];
+    const FinalSeg f = final_at(w, cls, q);
     const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
     const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
     const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
@@ -131,17 +132,19 @@ template <typename K, bool F32, bool PAY>
 int launch_rfis_class(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
                       uint32_t* pay_out, uint64_t cap_c, hipStream_t st) {
   const uint64_t slots = (uint64_t)num_cu_cached() * 16;
-  const uint32_t g1 = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots);
-  const uint32_t g2 = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots / 2);
-  switch (c) {
+  const bool dir = (c & kDirect) != 0;
+  const int ca = dir ? -1 : c;
+  const uint32_t g1 = dir ? 1u : (uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots);
+  const uint32_t g2 = dir ? 1u : (uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots / 2);
+  switch (c & 0xFF) {
     case 0:
-      RS_LAUNCH((k_rfis<K, F32, PAY, 64, 64>), g1, 64, st, w, c, kin, pay_in, kout, perm_out, pay_out);
+      RS_LAUNCH((k_rfis<K, F32, PAY, 64, 64>), g1, 64, st, w, ca, kin, pay_in, kout, perm_out, pay_out);
       break;
     case 1:
-      RS_LAUNCH((k_rfis<K, F32, PAY, 64, 256>), g1, 64, st, w, c, kin, pay_in, kout, perm_out, pay_out);
+      RS_LAUNCH((k_rfis<K, F32, PAY, 64, 256>), g1, 64, st, w, ca, kin, pay_in, kout, perm_out, pay_out);
       break;
     case 2:
-      RS_LAUNCH((k_rfis<K, F32, PAY, 256, 1024>), g2, 256, st, w, c, kin, pay_in, kout, perm_out, pay_out);
+      RS_LAUNCH((k_rfis<K, F32, PAY, 256, 1024>), g2, 256, st, w, ca, kin, pay_in, kout, perm_out, pay_out);
       break;
     default:
       return launch_merge_class<K, F32, PAY>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, st);
@@ -223,9 +226,10 @@ __global__ __launch_bounds__(THREADS) void k_rquick(Work w, int cls, const K* in
   __shared__ uint32_t off[P], len[P], xs[P], noff[P], nlen[P];
 
   const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
-  const uint32_t cnt = (uint32_t)min((uint64_t)w.ctl->class_count[cls], w.cls_cap[cls]);
+  direct_reset(w, cls);
+  const uint32_t cnt = final_count(w, cls);
   for (uint32_t q = blockIdx.x; q < cnt; q += gridDim.x) {
-    const FinalSeg f = w.cls[cls][q];
+    const FinalSeg f = final_at(w, cls, q);
     const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
     const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
     const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
@@ -415,14 +419,17 @@ int launch_rquick_class(int c, const Work& w, const K* kin, const uint32_t* pay_
                         uint32_t* pay_out, uint64_t cap_c, hipStream_t st) {
   const uint64_t slots = (uint64_t)num_cu_cached() * 2;
   const uint64_t seed = tuning().seed;
-  const uint32_t g = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots);
-  switch (c) {
+  const bool dir = (c & kDirect) != 0;
+  const int ca = dir ? -1 : c;
+  const uint32_t g = dir ? 1u : (uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots);
+  switch (c & 0xFF) {
     case 3:
-      RS_LAUNCH((k_rquick<K, F32, PAY, 512, 2048, 16>), g, 512, st, w, c, kin, pay_in, kout, perm_out, pay_out, seed);
+      RS_LAUNCH((k_rquick<K, F32, PAY, 512, 2048, 16>), g, 512, st, w, ca, kin, pay_in, kout, perm_out, pay_out, seed);
       break;
     case 4:
     case 5:
-      RS_LAUNCH((k_rquick<K, F32, PAY, 1024, 4096, 16>), g, 1024, st, w, c, kin, pay_in, kout, perm_out, pay_out, seed);
+      RS_LAUNCH((k_rquick<K, F32, PAY, 1024, 4096, 16>), g, 1024, st, w, ca, kin, pay_in, kout, perm_out, pay_out,
+                seed);
       break;
     default:
       return launch_merge_class<K, F32, PAY>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, st);

@@ -25,7 +25,7 @@ EXPORTS = [
     "rsort_segmented", "rsort_workspace_status", "rsort_stats", "rsort_get_tuning", "rsort_set_tuning",
     "rsort_server_create", "rsort_server_destroy", "rsort_submit", "rsort_poll", "rsort_wait", "rsort_release",
     "rsort_server_counters", "rsort_median_tree_workspace", "rsort_median_tree", "rsort_timing_begin",
-    "rsort_timing_end",
+    "rsort_timing_end", "rsort_class_stats", "rsort_server_request_bytes",
 ]
 
 
@@ -98,6 +98,10 @@ def lib():
         L.rsort_release.argtypes = [vp, u64]
         L.rsort_server_counters.restype = i32
         L.rsort_server_counters.argtypes = [vp] + [ctypes.POINTER(u64)] * 4
+        L.rsort_server_request_bytes.restype = sz
+        L.rsort_server_request_bytes.argtypes = [i32, u64]
+        L.rsort_class_stats.restype = i32
+        L.rsort_class_stats.argtypes = [vp, vp, u32, vp, vp, vp]
         L.rsort_timing_begin.restype = i32
         L.rsort_timing_end.restype = i32
         L.rsort_timing_end.argtypes = [u32, vp, u32, vp, vp, ctypes.POINTER(u32)]
@@ -224,6 +228,21 @@ def stats(workspace: torch.Tensor, stream=None) -> dict:
             "level_buckets": lb[:lv.value], "oversize": ov.value}
 
 
+def class_stats(workspace: torch.Tensor, stream=None) -> list:
+    """Per final-bucket size class: (largest bucket, buckets, keys) of the last
+    call that used this workspace."""
+    import numpy as np
+
+    m = 32
+    cm = np.zeros(m, np.uint32)
+    nb = np.zeros(m, np.uint32)
+    nk = np.zeros(m, np.uint64)
+    rc = lib().rsort_class_stats(_ptr(workspace), _stream(stream), m, cm.ctypes.data, nb.ctypes.data, nk.ctypes.data)
+    if rc < 0:
+        raise RsortError(rc, "rsort_class_stats")
+    return [(int(cm[i]), int(nb[i]), int(nk[i])) for i in range(rc)]
+
+
 # ----------------------------------------------------------------------------- tuning
 def get_tuning() -> Tuning:
     t = Tuning()
@@ -300,7 +319,13 @@ def median_tree(vals: torch.Tensor, per_problem: int, leaf_off: torch.Tensor, lo
 # ----------------------------------------------------------------------------- server
 class Server:
     """Continuous-batching sort server (rsort_server_*).  device < 0 uses the
-    host-only fake executor (admission logic only, buffers untouched)."""
+    host-only fake executor (admission logic only, buffers untouched).
+    hbm_budget_bytes is reserved at creation as the server's scratch arena."""
+
+    @staticmethod
+    def request_bytes(kt: int, n: int) -> int:
+        """Arena bytes a request of n keys takes when it runs alone."""
+        return int(lib().rsort_server_request_bytes(kt, n))
 
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 64 << 30, max_inflight: int = 8):
         h = ctypes.c_void_p()

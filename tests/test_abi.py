@@ -84,13 +84,18 @@ def fake_req(s, n, kt=R.U64, bad=False):
     return s.submit(kt, 0xBAD if bad else 0x1000, n, 0x100000, None)
 
 
+LARGE = 1 << 21  # above the small-request lane
+
+
 def test_server_admission_budget_and_tickets():
-    budget = 10 * (1 << 20) * 16  # 10 requests of 2^20 u64 keys (in + out)
+    per = R.Server.request_bytes(R.U64, LARGE)
+    assert per >= LARGE * 24  # two (key, index) buffers at least
+    budget = 10 * per  # arena for 10 requests of 2^21 u64 keys
     with R.Server(device=-1, hbm_budget_bytes=budget, max_inflight=4) as s:
         with pytest.raises(R.RsortError) as e:
             fake_req(s, budget)  # alone larger than the budget
         assert e.value.code == R.ENOMEM
-        tickets = [fake_req(s, 1 << 20) for _ in range(12)]
+        tickets = [fake_req(s, LARGE) for _ in range(12)]
         assert len(set(tickets)) == 12
         peak = 0
         while True:
@@ -111,9 +116,9 @@ def test_server_admission_budget_and_tickets():
 
 
 def test_server_fifo_and_memory_wait():
-    per = (1 << 20) * 16
+    per = R.Server.request_bytes(R.U64, LARGE)
     with R.Server(device=-1, hbm_budget_bytes=2 * per, max_inflight=8) as s:
-        ts = [fake_req(s, 1 << 20) for _ in range(6)]
+        ts = [fake_req(s, LARGE) for _ in range(6)]
         starts = []
         for t in ts:
             rc, r = s.wait(t, 5000)
@@ -136,6 +141,41 @@ def test_server_error_goes_to_its_ticket_only():
         assert s.wait(good2, 5000)[0] == R.OK
         zero = s.submit(R.U32, 0, 0, 0, None)
         assert s.poll(zero)[0] == R.OK
+
+
+def test_server_packs_small_requests():
+    # small requests queued behind a running batch are packed into one launch,
+    # grouped by key type, and each keeps its own ticket and status
+    with R.Server(device=-1, hbm_budget_bytes=1 << 34, max_inflight=2) as s:
+        kts = [R.U32, R.U64, R.F32]
+        ts = [(fake_req(s, 5000 + i, kt=kts[i % 3], bad=(i == 77)), kts[i % 3], i) for i in range(300)]
+        by_start = {}
+        for t, kt, i in ts:
+            rc, r = s.wait(t, 5000)
+            assert rc == (R.EDEVICE if i == 77 else R.OK)
+            assert 1 <= r.batch_size <= 1024
+            by_start.setdefault(r.t_start_ns, []).append((kt, r.batch_size))
+        assert max(len(v) for v in by_start.values()) > 1  # some batch packed several requests
+        for group in by_start.values():
+            assert len({kt for kt, _ in group}) == 1  # one key type per batch
+            assert all(b == len(group) for _, b in group)
+        c = s.counters()
+        assert c["finished"] == 300 and c["running"] == 0 and c["bytes_in_use"] == 0  # arena fully returned
+
+
+def test_server_arena_fragmentation_and_reuse():
+    # mixed sizes through a small arena: never over budget, every request
+    # finishes, and the arena coalesces back to one free block
+    sizes = [LARGE, 3 * LARGE, LARGE + 7, 5000, 2 * LARGE, 70000, LARGE, 1 << 20]
+    budget = R.Server.request_bytes(R.U64, 3 * LARGE) + R.Server.request_bytes(R.U64, LARGE)
+    with R.Server(device=-1, hbm_budget_bytes=budget, max_inflight=6) as s:
+        ts = [fake_req(s, sizes[i % len(sizes)]) for i in range(64)]
+        while s.counters()["finished"] < 64:
+            assert s.counters()["bytes_in_use"] <= budget
+            time.sleep(0.0002)
+        assert all(s.poll(t)[0] == R.OK for t in ts)
+        assert s.counters()["bytes_in_use"] == 0
+    assert R.Server.request_bytes(R.U64, 0) == 0 and R.Server.request_bytes(9, 10) == 0
 
 
 def test_server_rejects_bad_requests():

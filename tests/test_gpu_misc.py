@@ -118,3 +118,31 @@ def test_server_alone_equals_mix():
     assert max(r.batch_size for _, r in results) >= 1
     for (ak, ap), (ok, op) in zip(alone, outs):
         assert same_bits(ak, host(ok)) and np.array_equal(ap, host(op))
+
+
+def test_server_packed_small_requests_match_oracle():
+    """Hundreds of small requests (packed by the server into segmented sorts,
+    some keys-only, sizes 1..2^14, all key types) each equal the oracle's sort
+    of that request alone."""
+    rng = np.random.default_rng(9)
+    kts = ["u32", "u64", "f32"]
+    dists = ["uniform", "gaussian", "zero", "deterdupl", "reverse", "sorted"]
+    reqs = []
+    for i in range(400):
+        n = max(1, int(2 ** rng.uniform(0, 14)))
+        reqs.append((gen.keys(kts[i % 3], dists[i % 6], n, seed=1000 + i), i % 4 != 3))
+    banner("server packing %d small requests" % len(reqs))
+    ins = [dev(x) for x, _ in reqs]
+    outs = [(torch.empty_like(t), torch.empty(t.numel(), dtype=torch.uint32, device="cuda") if wp else None)
+            for t, (_, wp) in zip(ins, reqs)]
+    torch.cuda.synchronize()
+    with R.Server(device=0, hbm_budget_bytes=4 << 30, max_inflight=4) as s:
+        tickets = [s.submit_tensors(t, o[0], o[1]) for t, o in zip(ins, outs)]
+        results = [s.wait(t, 60000) for t in tickets]
+    assert all(rc == R.OK for rc, _ in results), [rc for rc, _ in results]
+    assert max(r.batch_size for _, r in results) > 1  # the server packed requests
+    for (x, wp), (ok, op) in zip(reqs, outs):
+        ek, ep, _ = O.sort(x)
+        assert same_bits(ek, host(ok))
+        if wp:
+            assert np.array_equal(ep, host(op))
