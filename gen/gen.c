@@ -22,6 +22,9 @@
  *   REVERSE    x_i = n - 1 - i
  *   SORTED     x_i = i
  *   TOPBITS    x_i = r_i >> (64 - param)          (param 3 gives 8 distinct values)
+ *   WIDEDUP    x_i = splitmix64(seed', r_i mod param) (param 0 means 300): few
+ *              distinct values spread over the whole key range, seed' = seed
+ *              xor 0xD1B54A32D192ED03
  * f32 keys: UNIFORM is a random 32-bit pattern (NaNs, infinities and signed
  * zeros occur); the others are the float value of the integer formula.
  */
@@ -40,6 +43,7 @@ enum {
   D_REVERSE = 4,
   D_SORTED = 5,
   D_TOPBITS = 6,
+  D_WIDEDUP = 7,
 };
 
 static inline uint64_t mix64(uint64_t z) {
@@ -115,6 +119,13 @@ int gen_keys(int kt, int dist, uint64_t param, uint64_t seed, uint64_t n, uint64
         vf = (float)v64;
         break;
       }
+      case D_WIDEDUP: {
+        uint64_t m = param ? param : 300;
+        v64 = gen_splitmix64(seed ^ 0xD1B54A32D192ED03ULL, gen_splitmix64(seed, s) % m);
+        v32 = (uint32_t)v64;
+        memcpy(&vf, &v32, 4);
+        break;
+      }
       default:
         break;
     }
@@ -125,7 +136,7 @@ int gen_keys(int kt, int dist, uint64_t param, uint64_t seed, uint64_t n, uint64
     else
       ((float *)out)[i] = vf;
   }
-  if (dist < D_UNIFORM || dist > D_TOPBITS) return -1;
+  if (dist < D_UNIFORM || dist > D_WIDEDUP) return -1;
   return 0;
 }
 

@@ -28,6 +28,7 @@ DISTS = {
     "reverse": 4,
     "sorted": 5,
     "topbits": 6,
+    "widedup": 7,
 }
 
 _lib = None

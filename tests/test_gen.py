@@ -32,6 +32,8 @@ def test_distribution_facts():
     g = gen.keys("u64", "gaussian", 1 << 18).astype(np.float64) - 2.0 ** 63
     z = g / 2.0 ** 40
     assert abs(z.mean()) < 0.01 and abs(z.std() - 1) < 0.01
+    wd = gen.keys("u64", "widedup", n, seed=4)
+    assert np.unique(wd).size == 300 and wd.max() > 1 << 62 and wd.min() < 1 << 58
 
 
 def test_log_uniform_sizes():

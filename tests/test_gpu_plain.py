@@ -32,6 +32,19 @@ def test_plain_parity(n, kt, dist):
     assert np.array_equal(po, ep)
 
 
+@pytest.mark.parametrize("n", [5000, 12289, 300007, (1 << 20) + 7, 1 << 22])
+@pytest.mark.parametrize("kt", ["u64", "u32"])
+def test_plain_wide_range_duplicates(n, kt):
+    """Few distinct keys spread over the whole key range: final buckets hold
+    runs of equal keys whose key range is too wide for exact single-word
+    compares, so the order among equal keys must come from their positions."""
+    x = gen.keys(kt, "widedup", n, seed=n + 11, param=300 if n > 5000 else 40)
+    ko, po = gpu_sort(x)
+    ek, ep, _ = O.sort(x)
+    assert same_bits(ko, ek)
+    assert np.array_equal(po, ep)
+
+
 def test_plain_keys_only_and_empty():
     x = gen.keys("u64", "uniform", 100000, seed=5)
     ko, po = gpu_sort(x, with_perm=False)
