@@ -186,3 +186,38 @@ def test_server_rejects_bad_requests():
             s.submit(R.U32, 0, 10, 0x2000, None)
     with pytest.raises(R.RsortError):
         R.Server(device=-1, hbm_budget_bytes=1 << 30, max_inflight=0)
+
+
+# ---------------------------------------------------------------- autotuner (host logic)
+def test_autotune_threshold_choice():
+    from paper_1606_08766_amd import autotune as A
+    # merge fastest everywhere: RFIS and RQuick turned off
+    t = {(b, "merge"): 1.0 for b in A.CLASS_BOUNDS}
+    t.update({(b, "rfis"): 2.0 for b in A.RFIS_BOUNDS})
+    t.update({(b, "rquick"): 3.0 for b in A.RQUICK_BOUNDS})
+    assert A.choose_thresholds(t)[:2] == (1, 1)
+    # RFIS wins up to 256, RQuick at 2048 and 3072: thresholds express exactly that
+    t[(64, "rfis")] = t[(256, "rfis")] = 0.5
+    t[(2048, "rquick")] = t[(3072, "rquick")] = 0.5
+    rf, rq, total = A.choose_thresholds(t)
+    assert (rf, rq) == (256, 3072)
+    assert total == pytest.approx(0.5 * 4 + 1.0 * (len(A.CLASS_BOUNDS) - 4))
+    # a non-contiguous winner set is approximated by the cheapest contiguous choice
+    t[(256, "rfis")] = 5.0
+    assert A.choose_thresholds(t)[0] == 64
+    assert A.algo_for(64, 256, 3072) == "rfis" and A.algo_for(4096, 256, 3072) == "merge"
+    assert A.algo_for(2048, 256, 3072) == "rquick"
+
+
+def test_autotune_save_load_roundtrip(tmp_path):
+    from paper_1606_08766_amd import autotune as A
+    saved = R.get_tuning()
+    try:
+        res = {"rfis_max": 64, "rquick_max": 2048, "tile_log2": 13, "oversample": 16, "target": 3072}
+        p = str(tmp_path / "t.json")
+        A.save(res, p)
+        A.load(p)
+        t = R.get_tuning()
+        assert (t.rfis_max, t.rquick_max, t.tile_log2, t.oversample, t.target) == (64, 2048, 13, 16, 3072)
+    finally:
+        R.set_tuning(**{f: getattr(saved, f) for f, _ in R.Tuning._fields_})

@@ -146,3 +146,27 @@ def test_server_packed_small_requests_match_oracle():
         assert same_bits(ek, host(ok))
         if wp:
             assert np.array_equal(ep, host(op))
+
+
+def test_autotuner_quick_run_keeps_parity():
+    """The autotuner measures and installs a tuning; sorting under it stays
+    bit-exact (tuning changes speed only)."""
+    from paper_1606_08766_amd import autotune as A
+    saved = R.get_tuning()
+    try:
+        banner("autotune quick")
+        res = A.tune("u64", quick=True)
+        assert res["rfis_max"] in (1, 64, 256, 1024) and res["rquick_max"] in (1, 2048, 3072, 4096)
+        assert res["tile_log2"] in (12, 13) and len(res["class_ns_per_key"]) >= 9
+        x = gen.keys("u64", "gaussian", (1 << 20) + 5, seed=77)
+        ko, po = gpu_sort(x)
+        ek, ep, _ = O.sort(x)
+        assert same_bits(ko, ek) and np.array_equal(po, ep)
+        sizes = gen.log_uniform_sizes(3000, 0, 13, seed=3)
+        keys, _, off = gen.segmented("u32", sizes, gen.pick_dists(3000, ["uniform", "zero", "deterdupl"], seed=4),
+                                     seed=5)
+        ko, po, _ = R.segmented_sort(dev(keys), dev(off.astype(np.int64)))
+        ek, ep = O.segmented(keys, off)[:2]
+        assert same_bits(host(ko), ek) and np.array_equal(host(po), ep)
+    finally:
+        R.set_tuning(**{f: getattr(saved, f) for f, _ in R.Tuning._fields_})
