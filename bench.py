@@ -139,10 +139,11 @@ def bench_plain(args, R, torch):
     if args.calib_copy_mib:
         # a plain device copy of known size, so that profiler byte counters
         # can be scaled by what they read for it
+        # (an elementwise kernel: reads cb bytes and writes cb bytes)
         cb = args.calib_copy_mib << 20
-        src = torch.empty(cb, dtype=torch.uint8, device="cuda")
+        src = torch.ones(cb // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     for s in range(args.warmup):
@@ -311,6 +312,43 @@ def bench_batched(args, R, torch):
         "plain_sample": "rsort_plain on the first %d segments (%d keys), keys + perm only" % (m, npl),
         "ms_per_pass": per,
     }
+
+
+def bench_latency(args, R, torch):
+    """Config 1: one plain sort of 2^20 uniform u64 keys (seed 1), single
+    level of 256 buckets then the local sorts; keys + permutation.  Each sort
+    is timed alone with events on the stream it runs on."""
+    import numpy as np
+
+    from gen import gen
+
+    n = 1 << 20
+    x = torch.from_numpy(gen.keys("u64", "uniform", n, seed=1)).cuda()
+    ws = torch.empty(R.plain_workspace_bytes(R.U64, n), dtype=torch.uint8, device="cuda")
+    ko = torch.empty_like(x)
+    po = torch.empty(n, dtype=torch.uint32, device="cuda")
+    for _ in range(max(args.warmup, 3)):
+        R.sort(x, workspace=ws, out=(ko, po))
+    torch.cuda.synchronize()
+    st = R.stats(ws)
+    us = []
+    for _ in range(max(args.steps, 20)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        R.sort(x, workspace=ws, out=(ko, po))
+        b.record()
+        b.synchronize()
+        us.append(a.elapsed_time(b) * 1e3)
+    us = np.array(us)
+    mean = float(us.mean())
+    return {"metric": "us per plain sort of 2^20 u64 keys (latency)", "value": round(mean, 2), "unit": "us",
+            "n_gpus": 1, "steps": int(us.size), "warmup": max(args.warmup, 3), "ms_per_step": round(mean / 1e3, 4),
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+            "data": "synthetic",
+            "config": {"workload": "plain sort of 2^20 uniform uint64 keys (seed 1), single level of 256 buckets",
+                       "n": n, "levels": int(st["levels"])},
+            "p50_us": round(float(np.percentile(us, 50)), 2), "min_us": round(float(us.min()), 2),
+            "gkeys_per_s": round(n / mean / 1e3, 3)}
 
 
 def bench_small(args, R, torch):
@@ -486,7 +524,7 @@ def pmc_summary(fetch_csv, write_csv, copy_mib, command, out_dir):
     plain copy of copy_mib MiB and write profiles/traffic.json + a text table."""
     f = _read_pmc(fetch_csv, "FETCH_SIZE")
     w = _read_pmc(write_csv, "WRITE_SIZE")
-    copy = [k for k in f if "copyBuffer" in k or "copy" in k.lower()]
+    copy = [k for k in f if "elementwise" in k.lower()]
     if not copy:
         raise SystemExit("no copy kernel found for calibration")
     ck = max(copy, key=lambda k: f[k][1])
@@ -554,7 +592,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n-log2", type=int, default=28)
-    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "small", "serving"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "latency", "batched", "small", "serving"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-variant", default="1gib", choices=["1gib", "literal"])
     ap.add_argument("--requests", type=int, default=2000)
@@ -578,6 +616,8 @@ def main():
 
     if args.workload == "plain":
         out = bench_plain(args, R, torch)
+    elif args.workload == "latency":
+        out = bench_latency(args, R, torch)
     elif args.workload == "batched":
         out = bench_batched(args, R, torch)
     elif args.workload == "small":

@@ -116,7 +116,7 @@ __global__ void k_init(Work w, const uint64_t* seg_off, uint32_t num_segs, uint6
   }
 }
 
-// Per level: tiles and count-matrix bases of the segments to split.
+// Per level: tile groups and count-matrix bases of the segments to split.
 constexpr int kPlanThreads = 1024;
 __global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev, uint32_t tile) {
   __shared__ uint32_t tmp[kPlanThreads / kWave + 1];
@@ -128,23 +128,23 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev, uint32_t
     const uint32_t i = base + threadIdx.x;
     uint32_t nt = 0, nc = 0;
     if (i < m) {
-      nt = (B[i].len + tile - 1) / tile;
+      nt = ((B[i].len + tile - 1) / tile + kGroupTiles - 1) / kGroupTiles;  // groups
       nc = nt << B[i].logk;
     }
     uint32_t tt, tc;
     const uint32_t et = block_excl_scan<kPlanThreads>(nt, tmp, &tt);
     const uint32_t ec = block_excl_scan<kPlanThreads>(nc, tmp, &tc);
     if (i < m) {
-      w.tile_base[i] = ct + et;
+      w.group_base[i] = ct + et;
       w.count_base[i] = cc + ec;
     }
     ct += tt;
     cc += tc;
   }
   if (threadIdx.x == 0) {
-    w.tile_base[m] = ct;
+    w.group_base[m] = ct;
     w.count_base[m] = cc;
-    w.ctl->total_tiles = ct;
+    w.ctl->total_groups = ct;
     w.ctl->total_counts = cc;
     w.ctl->big_count[cur ^ 1] = 0;
   }
@@ -287,43 +287,43 @@ __device__ __forceinline__ uint32_t find_seg(const uint32_t* base, uint32_t m, u
   return lo;
 }
 
-// XCD-aware tile order: workgroups are dispatched round-robin over the 8
-// XCDs, so workgroup g runs on XCD g % 8.  Each XCD owns a contiguous range
-// of tiles and each of its workgroups a contiguous sub-range: neighbouring
-// tiles write neighbouring parts of each bucket's output run (which then meet
-// in the same L2), and consecutive tiles of a workgroup mostly belong to the
-// same segment, whose splitter tree then stays in LDS.
-struct TileWalk {
+// XCD-aware order of tile groups: workgroups are dispatched round-robin over
+// the 8 XCDs, so workgroup g runs on XCD g % 8.  Each XCD owns a contiguous
+// range of groups and each of its workgroups a contiguous sub-range:
+// neighbouring groups write neighbouring parts of each bucket's output run
+// (which then meet in the same L2), and consecutive groups of a workgroup
+// mostly belong to the same segment, whose splitter tree then stays in LDS.
+struct GroupWalk {
   uint32_t next, end;
-  __device__ __forceinline__ TileWalk(uint32_t T) {
+  __device__ __forceinline__ GroupWalk(uint32_t G) {
     const uint32_t x = blockIdx.x & 7u, r = blockIdx.x >> 3, per = max(gridDim.x >> 3, 1u);
-    const uint64_t lo = ((uint64_t)T * x) >> 3, hi = ((uint64_t)T * (x + 1)) >> 3;
+    const uint64_t lo = ((uint64_t)G * x) >> 3, hi = ((uint64_t)G * (x + 1)) >> 3;
     next = (uint32_t)(lo + (hi - lo) * r / per);
     end = (uint32_t)(lo + (hi - lo) * (r + 1) / per);
   }
 };
 
-// Segment a tile belongs to, cached in LDS by the tile loops below.
+// Segment a tile group belongs to, cached in LDS by the group loops below.
 struct SegCache {
-  uint32_t s, tb, tb_end, cb, seg0, logk;
+  uint32_t s, gb, gb_end, cb, seg0, logk;
   uint64_t start, ubase;
   uint32_t len, pad;
 };
 
-// Make sc describe the segment holding `tile` (reloading its splitter tree
-// into tk/ti) if the tile lies outside the cached segment.  Contains
+// Make sc describe the segment holding `group` (reloading its splitter tree
+// into tk/ti) if the group lies outside the cached segment.  Contains
 // __syncthreads(); called by every thread of the block.
 template <typename K, int THREADS>
-__device__ __forceinline__ void seg_for_tile(const Work& w, int cur, uint32_t m, uint32_t tile, SegCache& sc, K* tk,
-                                             uint32_t* ti, bool need_seg0) {
-  if (tile >= sc.tb && tile < sc.tb_end) return;  // uniform: sc is in LDS
+__device__ __forceinline__ void seg_for_group(const Work& w, int cur, uint32_t m, uint32_t group, SegCache& sc,
+                                              K* tk, uint32_t* ti, bool need_seg0) {
+  if (group >= sc.gb && group < sc.gb_end) return;  // uniform: sc is in LDS
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t s = find_seg(w.tile_base, m, tile);
+    const uint32_t s = find_seg(w.group_base, m, group);
     const BigSeg bs = w.big[cur][s];
     sc.s = s;
-    sc.tb = w.tile_base[s];
-    sc.tb_end = w.tile_base[s + 1];
+    sc.gb = w.group_base[s];
+    sc.gb_end = w.group_base[s + 1];
     sc.cb = w.count_base[s];
     sc.seg0 = need_seg0 ? w.offsets[sc.cb] : 0u;
     sc.logk = bs.logk;
@@ -350,64 +350,70 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
   __shared__ SegCache sc;
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
-  const uint32_t T = w.ctl->total_tiles;
+  const uint32_t G = w.ctl->total_groups;
   const K* bkey = SRC_IN ? nullptr : (const K*)w.buf_key[src_buf];
   const uint32_t* bidx = SRC_IN ? nullptr : w.buf_idx[src_buf];
   const uint32_t lane = lane_id();
   if (threadIdx.x == 0) {
-    sc.tb = 1;
-    sc.tb_end = 0;  // empty: forces a load
+    sc.gb = 1;
+    sc.gb_end = 0;  // empty: forces a load
   }
   for (uint32_t i = threadIdx.x; i < kMaxK; i += THREADS) hist[i] = 0;
   __syncthreads();
-  for (TileWalk tw(T); tw.next < tw.end; tw.next++) {
-    const uint32_t tile = tw.next;
-    seg_for_tile<K, THREADS>(w, cur, m, tile, sc, tk, ti, false);
-    const uint32_t tl = tile - sc.tb;
-    const uint64_t base = sc.start + (uint64_t)tl * TILE;
-    const uint32_t cnt = min(TILE, sc.len - tl * TILE);
-    K key[ITEMS];
-    bool valid[ITEMS];
+  for (GroupWalk gw(G); gw.next < gw.end; gw.next++) {
+    const uint32_t group = gw.next;
+    seg_for_group<K, THREADS>(w, cur, m, group, sc, tk, ti, false);
+    const uint32_t gl = group - sc.gb;
+    const uint32_t nt = (sc.len + TILE - 1) / TILE;
+    const uint32_t t_end = min(nt, (gl + 1) * kGroupTiles);
+    // the group's histogram accumulates over its tiles
+    for (uint32_t tl = gl * kGroupTiles; tl < t_end; tl++) {
+      const uint64_t base = sc.start + (uint64_t)tl * TILE;
+      const uint32_t cnt = min(TILE, sc.len - tl * TILE);
+      K key[ITEMS];
+      bool valid[ITEMS];
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const uint32_t jj = i * THREADS + threadIdx.x;
-      valid[i] = jj < cnt;
-      key[i] = K(0);
-      if (valid[i]) {
-        if constexpr (SRC_IN)
-          key[i] = load_ord<K, F32>(in_keys, base + jj);
-        else
-          key[i] = bkey[base + jj];
+      for (int i = 0; i < ITEMS; i++) {
+        const uint32_t jj = i * THREADS + threadIdx.x;
+        valid[i] = jj < cnt;
+        key[i] = K(0);
+        if (valid[i]) {
+          if constexpr (SRC_IN)
+            key[i] = load_ord<K, F32>(in_keys, base + jj);
+          else
+            key[i] = bkey[base + jj];
+        }
       }
-    }
-    uint32_t b[ITEMS];
-    const uint64_t ub = sc.ubase;
-    classify_batch<K, ITEMS>(tk, ti, sc.logk, key, valid,
-                             [&](int i) -> uint32_t {
-                               const uint64_t pos = base + i * THREADS + threadIdx.x;
-                               if constexpr (SRC_IN)
-                                 return (uint32_t)(pos - ub);
-                               else
-                                 return bidx[pos];
-                             },
-                             b);
+      uint32_t b[ITEMS];
+      const uint64_t ub = sc.ubase;
+      classify_batch<K, ITEMS>(tk, ti, sc.logk, key, valid,
+                               [&](int i) -> uint32_t {
+                                 const uint64_t pos = base + i * THREADS + threadIdx.x;
+                                 if constexpr (SRC_IN)
+                                   return (uint32_t)(pos - ub);
+                                 else
+                                   return bidx[pos];
+                               },
+                               b);
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      // one atomic per wave when the whole wave falls into one bucket
-      const uint64_t act = __ballot(valid[i]);
-      const uint32_t b0 = (uint32_t)__shfl(b[i], __ffsll((unsigned long long)act) - 1, kWave);
-      const uint64_t same = __ballot(valid[i] && b[i] == b0);
-      if (act && same == act) {
-        if (lane == (uint32_t)(__ffsll((unsigned long long)act) - 1)) atomicAdd(&hist[b0], (uint32_t)__popcll(act));
-      } else if (valid[i]) {
-        atomicAdd(&hist[b[i]], 1u);
+      for (int i = 0; i < ITEMS; i++) {
+        // one atomic per wave when the whole wave falls into one bucket
+        const uint64_t act = __ballot(valid[i]);
+        const uint32_t b0 = (uint32_t)__shfl(b[i], __ffsll((unsigned long long)act) - 1, kWave);
+        const uint64_t same = __ballot(valid[i] && b[i] == b0);
+        if (act && same == act) {
+          if (lane == (uint32_t)(__ffsll((unsigned long long)act) - 1))
+            atomicAdd(&hist[b0], (uint32_t)__popcll(act));
+        } else if (valid[i]) {
+          atomicAdd(&hist[b[i]], 1u);
+        }
       }
     }
     __syncthreads();
     const uint32_t kk = 1u << sc.logk;
-    const uint32_t nt = sc.tb_end - sc.tb;
+    const uint32_t ng = sc.gb_end - sc.gb;
     for (uint32_t bb = threadIdx.x; bb < kk; bb += THREADS) {
-      w.counts[sc.cb + bb * nt + tl] = hist[bb];
+      w.counts[sc.cb + bb * ng + gl] = hist[bb];
       hist[bb] = 0;
     }
     __syncthreads();
@@ -489,12 +495,12 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
   __shared__ uint32_t tmp[THREADS / kWave + 1];
   __shared__ SegCache sc;
   __shared__ K stage[TILE];
+  __shared__ uint32_t stage32[TILE];
   __shared__ uint8_t stage_b[TILE];
-  uint32_t* stage32 = reinterpret_cast<uint32_t*>(stage);
 
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
-  const uint32_t T = w.ctl->total_tiles;
+  const uint32_t G = w.ctl->total_groups;
   const K* bkey = SRC_IN ? nullptr : (const K*)w.buf_key[src_buf];
   const uint32_t* bidx = SRC_IN ? nullptr : w.buf_idx[src_buf];
   const uint32_t* bpay = SRC_IN ? in_pay : w.buf_pay[src_buf];
@@ -503,105 +509,109 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
   uint32_t* dpay = w.buf_pay[dst_buf];
   const uint32_t lane = lane_id();
   if (threadIdx.x == 0) {
-    sc.tb = 1;
-    sc.tb_end = 0;  // empty: forces a load
+    sc.gb = 1;
+    sc.gb_end = 0;  // empty: forces a load
   }
   if (threadIdx.x < kMaxK) hist[threadIdx.x] = 0;
   __syncthreads();
 
-  for (TileWalk tw(T); tw.next < tw.end; tw.next++) {
-    const uint32_t tile = tw.next;
-    seg_for_tile<K, THREADS>(w, cur, m, tile, sc, tk, ti, true);
-    const uint32_t tl = tile - sc.tb;
-    const uint32_t nt = sc.tb_end - sc.tb;
+  for (GroupWalk gw(G); gw.next < gw.end; gw.next++) {
+    const uint32_t group = gw.next;
+    seg_for_group<K, THREADS>(w, cur, m, group, sc, tk, ti, true);
+    const uint32_t gl = group - sc.gb;
+    const uint32_t ng = sc.gb_end - sc.gb;
     const uint32_t kk = 1u << sc.logk;
-    // this tile's output offset of bucket threadIdx.x (loaded early, used after ranking)
-    uint64_t my_off = 0;
-    if (threadIdx.x < kk) my_off = sc.start + (uint64_t)(w.offsets[sc.cb + threadIdx.x * nt + tl] - sc.seg0);
-    const BigSeg bs{sc.start, sc.ubase, sc.len, sc.logk};
-    const uint64_t base = bs.start + (uint64_t)tl * TILE;
-    const uint32_t cnt = min(TILE, bs.len - tl * TILE);
-    K key[ITEMS];
-    uint32_t idx[ITEMS], pay[ITEMS], pos[ITEMS];
-    bool valid[ITEMS];
+    const uint32_t t_end = min((sc.len + TILE - 1) / TILE, (gl + 1) * kGroupTiles);
+    // where the group's part of bucket threadIdx.x starts; advanced by each
+    // tile's count, so the tiles' runs follow each other in group order
+    uint64_t run_off = 0;
+    if (threadIdx.x < kk) run_off = sc.start + (uint64_t)(w.offsets[sc.cb + threadIdx.x * ng + gl] - sc.seg0);
+    for (uint32_t tl = gl * kGroupTiles; tl < t_end; tl++) {
+      const BigSeg bs{sc.start, sc.ubase, sc.len, sc.logk};
+      const uint64_t base = bs.start + (uint64_t)tl * TILE;
+      const uint32_t cnt = min(TILE, bs.len - tl * TILE);
+      K key[ITEMS];
+      uint32_t idx[ITEMS], pay[ITEMS], pos[ITEMS];
+      bool valid[ITEMS];
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const uint32_t jj = i * THREADS + threadIdx.x;
-      valid[i] = jj < cnt;
-      key[i] = K(0);
-      idx[i] = 0;
-      pay[i] = 0;
-      if (valid[i]) {
-        if constexpr (SRC_IN) {
-          key[i] = load_ord<K, F32>(in_keys, base + jj);
-          idx[i] = (uint32_t)(base + jj - bs.ubase);
-        } else {
-          key[i] = bkey[base + jj];
-          idx[i] = bidx[base + jj];
+      for (int i = 0; i < ITEMS; i++) {
+        const uint32_t jj = i * THREADS + threadIdx.x;
+        valid[i] = jj < cnt;
+        key[i] = K(0);
+        idx[i] = 0;
+        pay[i] = 0;
+        if (valid[i]) {
+          if constexpr (SRC_IN) {
+            key[i] = load_ord<K, F32>(in_keys, base + jj);
+            idx[i] = (uint32_t)(base + jj - bs.ubase);
+          } else {
+            key[i] = bkey[base + jj];
+            idx[i] = bidx[base + jj];
+          }
+          if constexpr (PAY) pay[i] = bpay[base + jj];
         }
-        if constexpr (PAY) pay[i] = bpay[base + jj];
       }
-    }
-    uint32_t b[ITEMS];
-    classify_batch<K, ITEMS>(tk, ti, bs.logk, key, valid, [&](int i) -> uint32_t { return idx[i]; }, b);
-    // rank inside (tile, bucket): one LDS atomic per element, or one per wave
-    // when the whole wave falls into a single bucket (skewed inputs)
+      uint32_t b[ITEMS];
+      classify_batch<K, ITEMS>(tk, ti, bs.logk, key, valid, [&](int i) -> uint32_t { return idx[i]; }, b);
+      // rank inside (tile, bucket): one LDS atomic per element, or one per wave
+      // when the whole wave falls into a single bucket (skewed inputs)
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const uint64_t act = __ballot(valid[i]);
-      const uint32_t b0 = (uint32_t)__shfl(b[i], __ffsll((unsigned long long)act) - 1, kWave);
-      const uint64_t same = __ballot(valid[i] && b[i] == b0);
-      uint32_t r = 0;
-      if (act && same == act) {
-        const int leader = __ffsll((unsigned long long)act) - 1;
-        uint32_t basev = 0;
-        if (lane == (uint32_t)leader) basev = atomicAdd(&hist[b0], (uint32_t)__popcll(act));
-        basev = __shfl(basev, leader, kWave);
-        r = basev + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
-      } else if (valid[i]) {
-        r = atomicAdd(&hist[b[i]], 1u);
+      for (int i = 0; i < ITEMS; i++) {
+        const uint64_t act = __ballot(valid[i]);
+        const uint32_t b0 = (uint32_t)__shfl(b[i], __ffsll((unsigned long long)act) - 1, kWave);
+        const uint64_t same = __ballot(valid[i] && b[i] == b0);
+        uint32_t r = 0;
+        if (act && same == act) {
+          const int leader = __ffsll((unsigned long long)act) - 1;
+          uint32_t basev = 0;
+          if (lane == (uint32_t)leader) basev = atomicAdd(&hist[b0], (uint32_t)__popcll(act));
+          basev = __shfl(basev, leader, kWave);
+          r = basev + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
+        } else if (valid[i]) {
+          r = atomicAdd(&hist[b[i]], 1u);
+        }
+        pos[i] = valid[i] ? ((b[i] << 24) | r) : 0xFFFFFFFFu;  // r < TILE <= 2^24
       }
-      pos[i] = valid[i] ? ((b[i] << 24) | r) : 0xFFFFFFFFu;  // r < TILE <= 2^24
-    }
-    __syncthreads();
-    // exclusive scan of the tile histogram -> tile-local bucket starts
-    {
-      const uint32_t hv = threadIdx.x < kk ? hist[threadIdx.x] : 0u;
-      const uint32_t e = block_excl_scan<THREADS>(hv, tmp, nullptr);
-      if (threadIdx.x < kk) {
-        hist[threadIdx.x] = e;
-        gdelta[threadIdx.x] = my_off - e;
+      __syncthreads();
+      // exclusive scan of the tile histogram -> tile-local bucket starts
+      {
+        const uint32_t hv = threadIdx.x < kk ? hist[threadIdx.x] : 0u;
+        const uint32_t e = block_excl_scan<THREADS>(hv, tmp, nullptr);
+        if (threadIdx.x < kk) {
+          hist[threadIdx.x] = e;
+          gdelta[threadIdx.x] = run_off - e;
+          run_off += hv;
+        }
       }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      if (pos[i] != 0xFFFFFFFFu) {
-        const uint32_t bb = pos[i] >> 24;
-        const uint32_t p = hist[bb] + (pos[i] & 0xFFFFFFu);
-        pos[i] = p;
-        stage[p] = key[i];
-        stage_b[p] = (uint8_t)bb;
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x < kMaxK) hist[threadIdx.x] = 0;  // ready for the next tile
-    for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) dkey[gdelta[stage_b[p]] + p] = stage[p];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < ITEMS; i++)
-      if (pos[i] != 0xFFFFFFFFu) stage32[pos[i]] = idx[i];
-    __syncthreads();
-    for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) didx[gdelta[stage_b[p]] + p] = stage32[p];
-    if constexpr (PAY) {
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < ITEMS; i++)
-        if (pos[i] != 0xFFFFFFFFu) stage32[pos[i]] = pay[i];
+      for (int i = 0; i < ITEMS; i++) {
+        if (pos[i] != 0xFFFFFFFFu) {
+          const uint32_t bb = pos[i] >> 24;
+          const uint32_t p = hist[bb] + (pos[i] & 0xFFFFFFu);
+          pos[i] = p;
+          stage[p] = key[i];
+          stage32[p] = idx[i];
+          stage_b[p] = (uint8_t)bb;
+        }
+      }
       __syncthreads();
-      for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) dpay[gdelta[stage_b[p]] + p] = stage32[p];
+      if (threadIdx.x < kMaxK) hist[threadIdx.x] = 0;  // ready for the next tile
+      for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) {
+        const uint64_t g = gdelta[stage_b[p]] + p;
+        dkey[g] = stage[p];
+        didx[g] = stage32[p];
+      }
+      if constexpr (PAY) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++)
+          if (pos[i] != 0xFFFFFFFFu) stage32[pos[i]] = pay[i];
+        __syncthreads();
+        for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) dpay[gdelta[stage_b[p]] + p] = stage32[p];
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -623,11 +633,11 @@ __global__ void k_level_end(Work w, int lev, uint32_t cap, uint32_t target, int 
       const uint32_t kk = 1u << bs.logk;
       active = b < kk;
       if (active) {
-        const uint32_t nt = w.tile_base[s + 1] - w.tile_base[s];
+        const uint32_t ng = w.group_base[s + 1] - w.group_base[s];
         const uint32_t cb = w.count_base[s];
         const uint32_t seg0 = w.offsets[cb];
-        lo = w.offsets[cb + b * nt] - seg0;
-        const uint32_t hi = (b + 1 < kk) ? w.offsets[cb + (b + 1) * nt] - seg0 : bs.len;
+        lo = w.offsets[cb + b * ng] - seg0;
+        const uint32_t hi = (b + 1 < kk) ? w.offsets[cb + (b + 1) * ng] - seg0 : bs.len;
         len = hi - lo;
         if (lev == 0 && s == 0) w.ctl->l0_bucket[b] = len;
       }
@@ -684,8 +694,8 @@ size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, 
   const uint32_t levels = plan_levels(n, t, cap);
   const uint32_t tile = 1u << t.tile_log2;
   const uint64_t big_max = levels ? n / (cap + 1) + 1 : 0;
-  const uint64_t tiles_max = levels ? n / tile + big_max + 1 : 0;
-  const uint64_t count_max = tiles_max * kMaxK;
+  const uint64_t groups_max = levels ? n / ((uint64_t)tile * kGroupTiles) + big_max + 1 : 0;
+  const uint64_t count_max = groups_max * kMaxK;
   const uint64_t scan_blocks = count_max / kScanChunk + 2;
   const uint64_t final_max = (uint64_t)num_segs + (uint64_t)levels * kMaxK * big_max + 1;
   uint64_t off = 0;
@@ -723,7 +733,7 @@ size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, 
     w->ctl = (Ctl*)(base + o_ctl);
     w->big[0] = (BigSeg*)(base + o_big0);
     w->big[1] = (BigSeg*)(base + o_big1);
-    w->tile_base = (uint32_t*)(base + o_tb);
+    w->group_base = (uint32_t*)(base + o_tb);
     w->count_base = (uint32_t*)(base + o_cb);
     w->tree_key = base + o_tk;
     w->tree_idx = (uint32_t*)(base + o_ti);
@@ -813,7 +823,7 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
 
   const uint32_t tile_log2 = t.tile_log2 == 13 ? 13 : 12;
   const uint32_t tile = 1u << tile_log2;
-  const uint64_t tiles_max = n / tile + w.big_max + 1;
+  const uint64_t groups_max = n / ((uint64_t)tile * kGroupTiles) + w.big_max + 1;
   for (uint32_t lev = 0; lev < levels; lev++) {
     const int dst = lev & 1;
     const int src = (lev + 1) & 1;  // buffer written by the previous level
@@ -826,14 +836,14 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
       RS_LAUNCH((k_splitters<K, false, false, kSplThreads, kSplItems>), gs, kSplThreads, st, w, (int)lev, kin, src, a,
                 t.seed);
     }
-    // tiles: 256 threads x 16 keys (tile_log2 12) or 512 x 16 (tile_log2 13);
-    // the grid is a multiple of 8 for the XCD-aware tile walk
-    const uint32_t gt = std::max<uint32_t>(8u, grid_for(tiles_max, tile_log2 == 12 ? 8 : 4) & ~7u);
+    // tiles: 512 threads x 8 keys (tile_log2 12) or 512 x 16 (tile_log2 13);
+    // the grid is a multiple of 8 for the XCD-aware walk over tile groups
+    const uint32_t gt = std::max<uint32_t>(8u, grid_for(groups_max, tile_log2 == 12 ? 8 : 4) & ~7u);
     if (tile_log2 == 12) {
       if (lev == 0)
-        RS_LAUNCH((k_count<K, F32, true, 256, 16>), gt, 256, st, w, (int)lev, kin, src);
+        RS_LAUNCH((k_count<K, F32, true, 512, 8>), gt, 512, st, w, (int)lev, kin, src);
       else
-        RS_LAUNCH((k_count<K, false, false, 256, 16>), gt, 256, st, w, (int)lev, kin, src);
+        RS_LAUNCH((k_count<K, false, false, 512, 8>), gt, 512, st, w, (int)lev, kin, src);
     } else {
       if (lev == 0)
         RS_LAUNCH((k_count<K, F32, true, 512, 16>), gt, 512, st, w, (int)lev, kin, src);
@@ -846,9 +856,9 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
     RS_LAUNCH(k_scan_down, gsc, kScanThreads, st, w);
     if (tile_log2 == 12) {
       if (lev == 0)
-        RS_LAUNCH((k_scatter<K, F32, true, PAY, 256, 16>), gt, 256, st, w, (int)lev, kin, pay_in, src, dst);
+        RS_LAUNCH((k_scatter<K, F32, true, PAY, 512, 8>), gt, 512, st, w, (int)lev, kin, pay_in, src, dst);
       else
-        RS_LAUNCH((k_scatter<K, false, false, PAY, 256, 16>), gt, 256, st, w, (int)lev, kin, pay_in, src, dst);
+        RS_LAUNCH((k_scatter<K, false, false, PAY, 512, 8>), gt, 512, st, w, (int)lev, kin, pay_in, src, dst);
     } else {
       if (lev == 0)
         RS_LAUNCH((k_scatter<K, F32, true, PAY, 512, 16>), gt, 512, st, w, (int)lev, kin, pay_in, src, dst);

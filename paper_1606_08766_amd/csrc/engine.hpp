@@ -12,6 +12,9 @@ constexpr int kMaxK = 1 << kMaxLogK;
 constexpr int kMaxLevels = 8;
 constexpr int kNumClasses = 10;           // final-bucket size classes (see the class table in engine.hip)
 constexpr uint32_t kMaxOversample = 32;
+// Tiles of one segment are handled in aligned groups of kGroupTiles by one
+// workgroup; histograms and offsets are kept per (bucket, group).
+constexpr uint32_t kGroupTiles = 16;
 
 // A segment that the current level splits.
 struct BigSeg {
@@ -33,7 +36,7 @@ struct Ctl {
   int32_t status;                  // RSORT_OK or a device-detected error
   uint32_t levels;                 // levels enqueued by the host
   uint32_t big_count[2];           // ping-pong lists of segments to split
-  uint32_t total_tiles;            // tiles of the current level
+  uint32_t total_groups;           // tile groups of the current level
   uint32_t total_counts;           // entries of the current level's count matrix
   uint32_t class_count[kNumClasses];  // final segments per size class (last = oversize)
   uint32_t level_max[kMaxLevels];  // largest bucket created per level
@@ -51,7 +54,7 @@ struct Ctl {
 struct Work {
   Ctl* ctl;
   BigSeg* big[2];
-  uint32_t* tile_base;   // [big_max + 1]
+  uint32_t* group_base;  // [big_max + 1] first tile group of each segment
   uint32_t* count_base;  // [big_max + 1]
   void* tree_key;        // [big_max * kMaxK] (K), node t of segment s at s*kMaxK + t
   uint32_t* tree_idx;

@@ -170,3 +170,34 @@ def test_autotuner_quick_run_keeps_parity():
         assert same_bits(host(ko), ek) and np.array_equal(host(po), ep)
     finally:
         R.set_tuning(**{f: getattr(saved, f) for f, _ in R.Tuning._fields_})
+
+
+@pytest.mark.parametrize("n", [1024, 16384])
+def test_device_median_tree_reproduces_printed_rank_error(n):
+    """Figure 4 (Appendix H) on the device primitive: 2000 problems of n
+    distinct uniform 32-bit integers, two per leaf, k = 2, random coins; the
+    maximal rank error and the mean squared rank error land within the
+    sampling error of the printed binary-tree curve."""
+    import os
+    gold = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "median_tree_rank_error.txt")):
+        if line.strip() and not line.startswith("#"):
+            f = line.split()
+            gold[int(f[0])] = (float(f[1]), float(f[2]))
+    runs = 2000
+    rng = np.random.default_rng(n)
+    p = n // 2
+    vals = np.empty(runs * n, dtype=np.uint64)
+    for q in range(runs):
+        vals[q * n:(q + 1) * n] = rng.choice(1 << 32, size=n, replace=False)
+    offs = np.tile(np.arange(0, n + 1, 2, dtype=np.uint64), runs)
+    coins = rng.integers(0, 2, size=runs * (p + 1)).astype(np.uint8)
+    banner("device median tree, %d runs of n=%d" % (runs, n))
+    out = host(R.median_tree(dev(vals), n, dev(offs), p.bit_length() - 1, 2, dev(coins), runs))
+    assert (out[:, 1] == 0).all()
+    v = vals.reshape(runs, n)
+    ranks = (v < out[:, 0:1]).sum(axis=1)
+    errs = np.abs(ranks / (n - 1) - 0.5)
+    gmax, gvar = gold[n]
+    assert 0.75 * gmax <= errs.max() <= 1.3 * gmax
+    assert np.mean(errs ** 2) == pytest.approx(gvar, rel=0.15)
