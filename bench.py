@@ -80,7 +80,7 @@ def kernel_class(name: str) -> str:
         return "count_l1" if "F32, true" in name else "count_l2"
     if "k_scatter" in name:
         return "scatter_l1" if "F32, true" in name else "scatter_l2"
-    if any(s in name for s in ("k_local_sort", "k_rfis", "k_rquick", "k_oversize")):
+    if any(s in name for s in ("k_local_sort", "k_local_words", "k_rfis", "k_rquick", "k_oversize")):
         return "local_sort"
     if "k_splitters" in name:
         return "splitters"

@@ -360,4 +360,83 @@ __device__ __forceinline__ void lds_merge_sort(K (&k)[ITEMS], uint32_t (&v)[ITEM
   }
 }
 
+// ---------------------------------------------------------------------------
+// The padded LDS merge sort for plain 64-bit words (one value per element),
+// used on composite words that already encode the sort order.  Equal words
+// are interchangeable.  Half the LDS of a (key, position) pair sort per
+// element and one compare per step.
+// ---------------------------------------------------------------------------
+template <int ITEMS>
+__device__ __forceinline__ void reg_sort_words(uint64_t (&c)[ITEMS]) {
+#pragma unroll
+  for (int size = 2; size <= ITEMS; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool asc = (i & size) == 0;
+          const bool jl = c[j] < c[i];
+          cx_swap(c[i], c[j], asc ? jl : !jl);
+        }
+      }
+    }
+  }
+}
+
+// t: the thread's index in the block (a caller may pass a copy the compiler
+// cannot see through, so per-thread addresses are not hoisted out of its loop).
+template <int THREADS, int ITEMS>
+__device__ __forceinline__ void lds_merge_sort_words(uint64_t (&c)[ITEMS], uint32_t* lo, uint32_t* hi,
+                                                     int t = threadIdx.x) {
+  constexpr int N = THREADS * ITEMS;
+  reg_sort_words<ITEMS>(c);
+  auto word = [&](int q) -> uint64_t { return ((uint64_t)hi[q] << 32) | lo[q]; };
+#pragma unroll 1
+  for (int run = ITEMS; run < N; run <<= 1) {
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const int q = lpad(t * ITEMS + i);
+      lo[q] = (uint32_t)c[i];
+      hi[q] = (uint32_t)(c[i] >> 32);
+    }
+    __syncthreads();
+    const int first = (t * ITEMS) & ~(2 * run - 1);
+    const int a0 = first, b0 = first + run;
+    const int alen = (N - a0) < run ? (N - a0) : run;
+    const int blen = (N - b0) <= 0 ? 0 : ((N - b0) < run ? (N - b0) : run);
+    const int d = t * ITEMS - first;
+    int l = d > blen ? d - blen : 0;
+    int h = d < alen ? d : alen;
+    while (l < h) {
+      const int mid = (l + h) >> 1;
+      if (word(lpad(b0 + d - 1 - mid)) < word(lpad(a0 + mid)))
+        h = mid;
+      else
+        l = mid + 1;
+    }
+    int ai = l, bi = d - l;
+    uint64_t ca = ai < alen ? word(lpad(a0 + ai)) : 0ull;
+    uint64_t cb = bi < blen ? word(lpad(b0 + bi)) : 0ull;
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const bool takeA = ai < alen && (bi >= blen || !(cb < ca));
+      c[i] = takeA ? ca : cb;
+      const int na = takeA ? ai + 1 : ai, nb = takeA ? bi : bi + 1;
+      const bool more = takeA ? na < alen : nb < blen;
+      if (more) {
+        const uint64_t nc = word(lpad(takeA ? a0 + na : b0 + nb));
+        if (takeA)
+          ca = nc;
+        else
+          cb = nc;
+      }
+      ai = na;
+      bi = nb;
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace rs

@@ -28,8 +28,10 @@ struct BigSeg {
 struct FinalSeg {
   uint64_t start;
   uint32_t len;
-  uint32_t src;  // 0: caller input (positions implicit), 1: buffer A, 2: buffer B
+  uint32_t src;  // low byte: 0 caller input (positions implicit), 1 buffer A, 2 buffer B;
+                 // kPairsFlag: handed from the word sort to the pair sort
 };
+constexpr uint32_t kPairsFlag = 0x100;
 
 // Control block at the start of the workspace (all counters device-side).
 struct Ctl {

@@ -15,11 +15,19 @@ static inline uint32_t grid_for(uint64_t work, uint32_t per_cu) {
   return (uint32_t)std::max<uint64_t>(g, 1);
 }
 
+// Workgroup shape of a class kernel: THREADS x ITEMS elements.
+template <int THREADS, int ITEMS>
+struct Shape {
+  static constexpr int T = THREADS, I = ITEMS;
+};
+
 
 
 // ---------------------------------------------------------------------------
-// Final segments of one size class: one workgroup each, sorted in LDS.
-template <typename K, bool F32, bool PAY, int THREADS, int ITEMS>
+// Final segments of one size class: one workgroup each, sorted in LDS as
+// (key, position) pairs.  FLAGGED: only the segments the word sort below
+// handed over (kPairsFlag).
+template <typename K, bool F32, bool PAY, int THREADS, int ITEMS, bool FLAGGED = false>
 __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K* in_keys, const uint32_t* in_pay,
                                                         K* keys_out, uint32_t* perm_out, uint32_t* pay_out) {
   constexpr int N = THREADS * ITEMS;
@@ -32,7 +40,9 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
   direct_reset(w, cls);
   const uint32_t cnt_c = final_count(w, cls);
   for (uint32_t q = blockIdx.x; q < cnt_c; q += gridDim.x) {
-    const FinalSeg f = final_at(w, cls, q);
+    FinalSeg f = final_at(w, cls, q);
+    if (FLAGGED && !(f.src & kPairsFlag)) continue;  // uniform
+    f.src &= 0xFFu;
     const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
     const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
     const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
@@ -72,6 +82,130 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
       if constexpr (PAY) pay_out[f.start + j] = srcp[f.start + s_p[q]];
     }
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide minimum and maximum (every thread of the block calls).
+template <typename K, int THREADS>
+__device__ __forceinline__ void block_minmax(K& mn, K& mx, K* red) {
+  constexpr int NW = THREADS / kWave;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const K a = __shfl_xor(mn, o, kWave), b = __shfl_xor(mx, o, kWave);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  const int wv = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    red[wv] = mn;
+    red[NW + wv] = mx;
+  }
+  __syncthreads();
+  mn = red[0];
+  mx = red[NW];
+#pragma unroll
+  for (int i = 1; i < NW; i++) {
+    mn = red[i] < mn ? red[i] : mn;
+    mx = red[NW + i] > mx ? red[NW + i] : mx;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Final segments of one size class sorted as single 64-bit words.  With mn the
+// segment's smallest key and rb the bit width of (largest key - mn), and PB
+// the bit width of a slot (the element's place in the segment as stored):
+//   exact words   rb + 32 (+ PB with payload) <= 64: the word
+//                 (key - mn, position [, slot]) orders exactly like the
+//                 (key, position) pair;
+//   slot words    rb + PB <= 64: the word (key - mn, slot); equal keys then
+//                 come out in slot order, which is checked against their
+//                 positions afterwards.
+// A segment that fits neither, or whose check finds equal keys out of
+// position order, is marked kPairsFlag and sorted by k_local_sort<FLAGGED>
+// launched next.  Every path produces the same output; words take half the
+// LDS of pairs and one compare per merge step.
+template <typename K, bool F32, bool PAY, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const K* in_keys, const uint32_t* in_pay,
+                                                         K* keys_out, uint32_t* perm_out, uint32_t* pay_out) {
+  constexpr int N = THREADS * ITEMS;
+  constexpr int NP = lpad_size(N);
+  constexpr int PB = 32 - __builtin_clz((unsigned)(N - 1));
+  constexpr uint64_t SLOT = (1ull << PB) - 1;
+  constexpr int XB = PAY ? PB : 0;  // slot bits kept in exact words (payload gather)
+  __shared__ uint32_t s_lo[NP];
+  __shared__ uint32_t s_hi[NP];
+  __shared__ K s_red[2 * (THREADS / kWave)];
+  const uint32_t cnt_c = final_count(w, cls);
+  for (uint32_t q = blockIdx.x; q < cnt_c; q += gridDim.x) {
+    const FinalSeg f = final_at(w, cls, q);
+    // an opaque copy of the thread index: per-thread addresses are recomputed
+    // per segment rather than hoisted out of the loop and kept live
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
+    const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
+    const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
+    auto idx_at = [&](uint32_t j) -> uint32_t { return f.src ? srci[f.start + j] : j; };
+    // thread t takes slots i*THREADS+t (striped, coalesced)
+    K k[ITEMS];
+    K mn = KMax<K>::v, mx = K(0);
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const uint32_t j = i * THREADS + tid;
+      if (j < f.len) {
+        k[i] = f.src ? srck[f.start + j] : load_ord<K, F32>(srck, f.start + j);
+        mn = k[i] < mn ? k[i] : mn;
+        mx = k[i] > mx ? k[i] : mx;
+      }
+    }
+    block_minmax<K, THREADS>(mn, mx, s_red);
+    const uint64_t range = (uint64_t)(mx - mn);
+    const int rb = range ? 64 - __clzll((long long)range) : 0;
+    const bool exact = rb + 32 + XB <= 64;
+    if (!exact && rb + PB > 64) {
+      if (threadIdx.x == 0) w.cls[cls][q].src = f.src | kPairsFlag;
+      continue;  // uniform
+    }
+    const int sh = exact ? 32 + XB : PB;
+    uint64_t c[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const uint32_t j = i * THREADS + tid;
+      uint64_t low = j;
+      if (exact) low = ((uint64_t)(j < f.len ? idx_at(j) : 0u) << XB) | (PAY ? j : 0u);
+      c[i] = j < f.len ? ((uint64_t)(k[i] - mn) << sh) | low : ~0ull;
+    }
+    lds_merge_sort_words<THREADS, ITEMS>(c, s_lo, s_hi, tid);
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const int qq = lpad(tid * ITEMS + i);
+      s_lo[qq] = (uint32_t)c[i];
+      s_hi[qq] = (uint32_t)(c[i] >> 32);
+    }
+    __syncthreads();
+    bool bad = false;
+    for (uint32_t j = tid; j < f.len; j += THREADS) {
+      const int qq = lpad(j);
+      const uint64_t cj = ((uint64_t)s_hi[qq] << 32) | s_lo[qq];
+      const uint32_t slot = (uint32_t)(cj & SLOT);
+      uint32_t idx;
+      if (exact) {
+        idx = (uint32_t)(cj >> XB);
+      } else {
+        idx = idx_at(slot);
+        if (j + 1 < f.len) {
+          const int qn = lpad(j + 1);
+          const uint64_t cn = ((uint64_t)s_hi[qn] << 32) | s_lo[qn];
+          if ((cn >> PB) == (cj >> PB) && idx_at((uint32_t)(cn & SLOT)) < idx) bad = true;
+        }
+      }
+      keys_out[f.start + j] = to_output<K, F32>((K)(mn + (K)(cj >> sh)));
+      if (perm_out) perm_out[f.start + j] = idx;
+      if constexpr (PAY) pay_out[f.start + j] = srcp[f.start + slot];
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) w.cls[cls][q].src = f.src | kPairsFlag;
   }
 }
 
@@ -193,48 +327,48 @@ __global__ __launch_bounds__(THREADS) void k_oversize(Work w, const K* in_keys, 
   }
 }
 
-// Local sort of one class with the merge sort.
+// Local sort of one class with the merge sort.  A one-segment direct sort
+// runs the pair sort alone; a class list runs the word sort and then the pair
+// sort over the segments the word sort handed over.
+#ifndef RS_WORDS_PER_CU
+#define RS_WORDS_PER_CU 64
+#endif
+template <typename K, bool F32, bool PAY, int T, int I>
+static int merge_class_launch(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout,
+                              uint32_t* perm_out, uint32_t* pay_out, uint64_t cap_c, uint32_t per,
+                              hipStream_t st) {
+  if (c & kDirect) {
+    RS_LAUNCH((k_local_sort<K, F32, PAY, T, I>), 1, T, st, w, -1, kin, pay_in, kout, perm_out, pay_out);
+    return 0;
+  }
+  // the word sort takes about one workgroup per segment (bounded); the pair
+  // sort of the rare handed-over segments a resident-sized grid
+  RS_LAUNCH((k_local_words<K, F32, PAY, T, I>), grid_for(cap_c, RS_WORDS_PER_CU), T, st, w, c, kin, pay_in, kout,
+            perm_out, pay_out);
+  RS_LAUNCH((k_local_sort<K, F32, PAY, T, I, true>), grid_for(cap_c, per), T, st, w, c, kin, pay_in, kout,
+            perm_out, pay_out);
+  return 0;
+}
+
 template <typename K, bool F32, bool PAY>
 int launch_merge_class(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
                        uint32_t* pay_out, uint64_t cap_c, hipStream_t st) {
-  const int ca = (c & kDirect) ? -1 : c;  // kernel class argument
-  auto gfc = [&](uint64_t cc, uint32_t per) { return (c & kDirect) ? 1u : grid_for(cc, per); };
-  switch (c & 0xFF) {
-    case 0:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 64, 1>), gfc(cap_c, 16), 64, st, w, ca, kin, pay_in, kout, perm_out, pay_out);
-      break;
-    case 1:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 64, 4>), gfc(cap_c, 16), 64, st, w, ca, kin, pay_in, kout, perm_out, pay_out);
-      break;
-    case 2:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 256, 4>), gfc(cap_c, 8), 256, st, w, ca, kin, pay_in, kout, perm_out,
-                pay_out);
-      break;
-    case 3:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 256, 8>), gfc(cap_c, 8), 256, st, w, ca, kin, pay_in, kout, perm_out,
-                pay_out);
-      break;
-    case 4:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 384, 8>), gfc(cap_c, 4), 384, st, w, ca, kin, pay_in, kout, perm_out,
-                pay_out);
-      break;
-    case 5:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 512, 8>), gfc(cap_c, 3), 512, st, w, ca, kin, pay_in, kout, perm_out,
-                pay_out);
-      break;
-    case 6:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 768, 8>), gfc(cap_c, 2), 768, st, w, ca, kin, pay_in, kout, perm_out,
-                pay_out);
-      break;
-    case 7:
-      RS_LAUNCH((k_local_sort<K, F32, PAY, 1024, 8>), gfc(cap_c, 1), 1024, st, w, ca, kin, pay_in, kout, perm_out,
-                pay_out);
-      break;
+  const int cb = c & 0xFF;
+  auto go = [&](auto tag, uint32_t per) -> int {
+    constexpr int T = decltype(tag)::T, I = decltype(tag)::I;
+    return merge_class_launch<K, F32, PAY, T, I>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, per, st);
+  };
+  switch (cb) {
+    case 0: return go(Shape<64, 1>{}, 16);
+    case 1: return go(Shape<64, 4>{}, 16);
+    case 2: return go(Shape<256, 4>{}, 8);
+    case 3: return go(Shape<256, 8>{}, 8);
+    case 4: return go(Shape<384, 8>{}, 4);
+    case 5: return go(Shape<512, 8>{}, 3);
+    case 6: return go(Shape<768, 8>{}, 2);
+    case 7: return go(Shape<1024, 8>{}, 1);
     case 8:
-      if constexpr (!PAY) {
-        RS_LAUNCH((k_local_sort<K, F32, PAY, 768, 16>), gfc(cap_c, 1), 768, st, w, ca, kin, pay_in, kout, perm_out,
-                  pay_out);
-      }
+      if constexpr (!PAY) return go(Shape<768, 16>{}, 1);
       break;
     default:
       break;
