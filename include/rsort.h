@@ -142,7 +142,7 @@ typedef struct {
   uint32_t rfis_max;     /* segments <= rfis_max use RFIS (0 disables: set 1) */
   uint32_t rquick_max;   /* segments <= rquick_max (and > rfis_max) use RQuick */
   uint64_t seed;         /* seed of the sample positions and coin flips */
-  uint32_t tile_log2;    /* log2 of elements per count/scatter tile (12 or 13) */
+  uint32_t tile_log2;    /* log2 of keys per scatter tile (12 or 13; counting uses 12) */
   uint32_t force_fallback; /* debug: 1 = every final bucket > 64 takes the
                               global-memory fallback sort, 2 = off (0 keeps) */
 } rsort_tuning;

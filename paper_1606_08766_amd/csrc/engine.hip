@@ -118,7 +118,7 @@ __global__ void k_init(Work w, const uint64_t* seg_off, uint32_t num_segs, uint6
 
 // Per level: tile groups and count-matrix bases of the segments to split.
 constexpr int kPlanThreads = 1024;
-__global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev, uint32_t tile) {
+__global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev) {
   __shared__ uint32_t tmp[kPlanThreads / kWave + 1];
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev, uint32_t
     const uint32_t i = base + threadIdx.x;
     uint32_t nt = 0, nc = 0;
     if (i < m) {
-      nt = ((B[i].len + tile - 1) / tile + kGroupTiles - 1) / kGroupTiles;  // groups
+      nt = (B[i].len + kGroupKeys - 1) / kGroupKeys;  // groups
       nc = nt << B[i].logk;
     }
     uint32_t tt, tc;
@@ -344,6 +344,8 @@ __device__ __forceinline__ void seg_for_group(const Work& w, int cur, uint32_t m
 template <typename K, bool F32, bool SRC_IN, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_keys, int src_buf) {
   constexpr uint32_t TILE = THREADS * ITEMS;
+  constexpr uint32_t GT = kGroupKeys / TILE;  // tiles per group
+  static_assert(GT * TILE == kGroupKeys, "tiles divide a group");
   __shared__ K tk[kMaxK];
   __shared__ uint32_t ti[kMaxK];
   __shared__ uint32_t hist[kMaxK];
@@ -365,9 +367,9 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
     seg_for_group<K, THREADS>(w, cur, m, group, sc, tk, ti, false);
     const uint32_t gl = group - sc.gb;
     const uint32_t nt = (sc.len + TILE - 1) / TILE;
-    const uint32_t t_end = min(nt, (gl + 1) * kGroupTiles);
+    const uint32_t t_end = min(nt, (gl + 1) * GT);
     // the group's histogram accumulates over its tiles
-    for (uint32_t tl = gl * kGroupTiles; tl < t_end; tl++) {
+    for (uint32_t tl = gl * GT; tl < t_end; tl++) {
       const uint64_t base = sc.start + (uint64_t)tl * TILE;
       const uint32_t cnt = min(TILE, sc.len - tl * TILE);
       K key[ITEMS];
@@ -487,6 +489,8 @@ template <typename K, bool F32, bool SRC_IN, bool PAY, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* in_keys, const uint32_t* in_pay,
                                                      int src_buf, int dst_buf) {
   constexpr uint32_t TILE = THREADS * ITEMS;
+  constexpr uint32_t GT = kGroupKeys / TILE;  // tiles per group
+  static_assert(GT * TILE == kGroupKeys, "tiles divide a group");
   static_assert(THREADS >= kMaxK, "one histogram bin per thread");
   __shared__ K tk[kMaxK];
   __shared__ uint32_t ti[kMaxK];
@@ -521,12 +525,12 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
     const uint32_t gl = group - sc.gb;
     const uint32_t ng = sc.gb_end - sc.gb;
     const uint32_t kk = 1u << sc.logk;
-    const uint32_t t_end = min((sc.len + TILE - 1) / TILE, (gl + 1) * kGroupTiles);
+    const uint32_t t_end = min((sc.len + TILE - 1) / TILE, (gl + 1) * GT);
     // where the group's part of bucket threadIdx.x starts; advanced by each
     // tile's count, so the tiles' runs follow each other in group order
     uint64_t run_off = 0;
     if (threadIdx.x < kk) run_off = sc.start + (uint64_t)(w.offsets[sc.cb + threadIdx.x * ng + gl] - sc.seg0);
-    for (uint32_t tl = gl * kGroupTiles; tl < t_end; tl++) {
+    for (uint32_t tl = gl * GT; tl < t_end; tl++) {
       const BigSeg bs{sc.start, sc.ubase, sc.len, sc.logk};
       const uint64_t base = bs.start + (uint64_t)tl * TILE;
       const uint32_t cnt = min(TILE, bs.len - tl * TILE);
@@ -692,9 +696,8 @@ size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, 
   const uint64_t ks = kt == 1 ? 8 : 4;
   const uint32_t cap = effective_cap(t, pay);
   const uint32_t levels = plan_levels(n, t, cap);
-  const uint32_t tile = 1u << t.tile_log2;
   const uint64_t big_max = levels ? n / (cap + 1) + 1 : 0;
-  const uint64_t groups_max = levels ? n / ((uint64_t)tile * kGroupTiles) + big_max + 1 : 0;
+  const uint64_t groups_max = levels ? n / kGroupKeys + big_max + 1 : 0;
   const uint64_t count_max = groups_max * kMaxK;
   const uint64_t scan_blocks = count_max / kScanChunk + 2;
   const uint64_t final_max = (uint64_t)num_segs + (uint64_t)levels * kMaxK * big_max + 1;
@@ -821,14 +824,13 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
   RS_LAUNCH(k_reset, 1, 256, st, w.ctl, levels);
   RS_LAUNCH(k_init, grid_for((num_segs + 255) / 256, 4), 256, st, w, seg_off, num_segs, n, cap, target, levels, ff);
 
-  const uint32_t tile_log2 = t.tile_log2 == 13 ? 13 : 12;
-  const uint32_t tile = 1u << tile_log2;
-  const uint64_t groups_max = n / ((uint64_t)tile * kGroupTiles) + w.big_max + 1;
+  const uint32_t tile_log2 = t.tile_log2 == 12 ? 12 : 13;
+  const uint64_t groups_max = n / kGroupKeys + w.big_max + 1;
   for (uint32_t lev = 0; lev < levels; lev++) {
     const int dst = lev & 1;
     const int src = (lev + 1) & 1;  // buffer written by the previous level
     const bool last = lev + 1 == levels;
-    RS_LAUNCH(k_plan, 1, kPlanThreads, st, w, (int)lev, tile);
+    RS_LAUNCH(k_plan, 1, kPlanThreads, st, w, (int)lev);
     const uint32_t gs = grid_for(w.big_max, 4);
     if (lev == 0) {
       RS_LAUNCH((k_splitters<K, F32, true, kSplThreads, kSplItems>), gs, kSplThreads, st, w, (int)lev, kin, src, a, t.seed);
@@ -836,34 +838,29 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
       RS_LAUNCH((k_splitters<K, false, false, kSplThreads, kSplItems>), gs, kSplThreads, st, w, (int)lev, kin, src, a,
                 t.seed);
     }
-    // tiles: 512 threads x 8 keys (tile_log2 12) or 512 x 16 (tile_log2 13);
-    // the grid is a multiple of 8 for the XCD-aware walk over tile groups
-    const uint32_t gt = std::max<uint32_t>(8u, grid_for(groups_max, tile_log2 == 12 ? 8 : 4) & ~7u);
-    if (tile_log2 == 12) {
-      if (lev == 0)
-        RS_LAUNCH((k_count<K, F32, true, 512, 8>), gt, 512, st, w, (int)lev, kin, src);
-      else
-        RS_LAUNCH((k_count<K, false, false, 512, 8>), gt, 512, st, w, (int)lev, kin, src);
-    } else {
-      if (lev == 0)
-        RS_LAUNCH((k_count<K, F32, true, 512, 16>), gt, 512, st, w, (int)lev, kin, src);
-      else
-        RS_LAUNCH((k_count<K, false, false, 512, 16>), gt, 512, st, w, (int)lev, kin, src);
-    }
+    // count tiles: 512 threads x 8 keys; scatter tiles: 512 x 8 (tile_log2
+    // 12) or 1024 x 8 (tile_log2 13); both walk the same groups of
+    // kGroupKeys keys.  Grids are multiples of 8 for the XCD-aware walk.
+    const uint32_t gt = std::max<uint32_t>(8u, grid_for(groups_max, 8) & ~7u);
+    const uint32_t gs_sc = std::max<uint32_t>(8u, grid_for(groups_max, tile_log2 == 12 ? 8 : 4) & ~7u);
+    if (lev == 0)
+      RS_LAUNCH((k_count<K, F32, true, 512, 8>), gt, 512, st, w, (int)lev, kin, src);
+    else
+      RS_LAUNCH((k_count<K, false, false, 512, 8>), gt, 512, st, w, (int)lev, kin, src);
     const uint32_t gsc = grid_for(w.count_max / kScanChunk + 1, 8);
     RS_LAUNCH(k_scan_reduce, gsc, kScanThreads, st, w);
     RS_LAUNCH(k_scan_partials, 1, kScanTopThreads, st, w);
     RS_LAUNCH(k_scan_down, gsc, kScanThreads, st, w);
     if (tile_log2 == 12) {
       if (lev == 0)
-        RS_LAUNCH((k_scatter<K, F32, true, PAY, 512, 8>), gt, 512, st, w, (int)lev, kin, pay_in, src, dst);
+        RS_LAUNCH((k_scatter<K, F32, true, PAY, 512, 8>), gs_sc, 512, st, w, (int)lev, kin, pay_in, src, dst);
       else
-        RS_LAUNCH((k_scatter<K, false, false, PAY, 512, 8>), gt, 512, st, w, (int)lev, kin, pay_in, src, dst);
+        RS_LAUNCH((k_scatter<K, false, false, PAY, 512, 8>), gs_sc, 512, st, w, (int)lev, kin, pay_in, src, dst);
     } else {
       if (lev == 0)
-        RS_LAUNCH((k_scatter<K, F32, true, PAY, 512, 16>), gt, 512, st, w, (int)lev, kin, pay_in, src, dst);
+        RS_LAUNCH((k_scatter<K, F32, true, PAY, 1024, 8>), gs_sc, 1024, st, w, (int)lev, kin, pay_in, src, dst);
       else
-        RS_LAUNCH((k_scatter<K, false, false, PAY, 512, 16>), gt, 512, st, w, (int)lev, kin, pay_in, src, dst);
+        RS_LAUNCH((k_scatter<K, false, false, PAY, 1024, 8>), gs_sc, 1024, st, w, (int)lev, kin, pay_in, src, dst);
     }
     RS_LAUNCH(k_level_end, grid_for((w.big_max * kMaxK + 255) / 256, 4), 256, st, w, (int)lev, cap, target,
               last ? 1 : 0, (uint32_t)(dst + 1), ff);

@@ -12,9 +12,10 @@ constexpr int kMaxK = 1 << kMaxLogK;
 constexpr int kMaxLevels = 8;
 constexpr int kNumClasses = 10;           // final-bucket size classes (see the class table in engine.hip)
 constexpr uint32_t kMaxOversample = 32;
-// Tiles of one segment are handled in aligned groups of kGroupTiles by one
-// workgroup; histograms and offsets are kept per (bucket, group).
-constexpr uint32_t kGroupTiles = 16;
+// A segment's keys are handled in aligned groups of kGroupKeys keys, each by
+// one workgroup; histograms and offsets are kept per (bucket, group), so the
+// count and scatter passes may use different tile sizes inside a group.
+constexpr uint32_t kGroupKeys = 1u << 17;
 
 // A segment that the current level splits.
 struct BigSeg {

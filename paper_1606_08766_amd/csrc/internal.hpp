@@ -17,7 +17,7 @@ struct Tuning {
   uint32_t rfis_max = 256;    // classes with upper bound <= rfis_max use RFIS
   uint32_t rquick_max = 1;    // classes with upper bound <= rquick_max use RQuick
   uint64_t seed = 0x5EED5EED12345678ull;
-  uint32_t tile_log2 = 12;
+  uint32_t tile_log2 = 13;  // scatter tile: 2^tile_log2 keys
   uint32_t force_fallback = 0;
 };
 
@@ -79,11 +79,15 @@ void timing_before(hipStream_t st);
 void timing_after(const char* tag, hipStream_t st);
 }  // namespace rs
 
-#define RS_LAUNCH(kern, grid, block, stream, ...)                                             \
+#define RS_LAUNCH(kern, grid, block, stream, ...) RS_LAUNCH_TAGGED(kern, #kern, grid, block, stream, __VA_ARGS__)
+
+// Same, with an explicit timing tag (for launches whose shape is a template
+// parameter of the launching function).
+#define RS_LAUNCH_TAGGED(kern, tag, grid, block, stream, ...)                                 \
   do {                                                                                        \
     const bool rs_t_ = ::rs::timing_enabled();                                                \
     if (rs_t_) ::rs::timing_before((hipStream_t)(stream));                                    \
     hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (hipStream_t)(stream), __VA_ARGS__); \
     if (hipPeekAtLastError() != hipSuccess) return -3;                                        \
-    if (rs_t_) ::rs::timing_after(#kern, (hipStream_t)(stream));                              \
+    if (rs_t_) ::rs::timing_after(tag, (hipStream_t)(stream));                                \
   } while (0)

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <string>
 
 #include "device.hpp"
 #include "engine.hpp"
@@ -337,16 +338,21 @@ template <typename K, bool F32, bool PAY, int T, int I>
 static int merge_class_launch(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout,
                               uint32_t* perm_out, uint32_t* pay_out, uint64_t cap_c, uint32_t per,
                               hipStream_t st) {
+  static const std::string shape = std::to_string(T) + ", " + std::to_string(I);
+  static const std::string t_pairs = "(k_local_sort<K, F32, PAY, " + shape + ">)";
+  static const std::string t_words = "(k_local_words<K, F32, PAY, " + shape + ">)";
+  static const std::string t_flagged = "(k_local_sort<K, F32, PAY, " + shape + ", true>)";
   if (c & kDirect) {
-    RS_LAUNCH((k_local_sort<K, F32, PAY, T, I>), 1, T, st, w, -1, kin, pay_in, kout, perm_out, pay_out);
+    RS_LAUNCH_TAGGED((k_local_sort<K, F32, PAY, T, I>), t_pairs.c_str(), 1, T, st, w, -1, kin, pay_in, kout,
+                     perm_out, pay_out);
     return 0;
   }
   // the word sort takes about one workgroup per segment (bounded); the pair
   // sort of the rare handed-over segments a resident-sized grid
-  RS_LAUNCH((k_local_words<K, F32, PAY, T, I>), grid_for(cap_c, RS_WORDS_PER_CU), T, st, w, c, kin, pay_in, kout,
-            perm_out, pay_out);
-  RS_LAUNCH((k_local_sort<K, F32, PAY, T, I, true>), grid_for(cap_c, per), T, st, w, c, kin, pay_in, kout,
-            perm_out, pay_out);
+  RS_LAUNCH_TAGGED((k_local_words<K, F32, PAY, T, I>), t_words.c_str(), grid_for(cap_c, RS_WORDS_PER_CU), T, st, w,
+                   c, kin, pay_in, kout, perm_out, pay_out);
+  RS_LAUNCH_TAGGED((k_local_sort<K, F32, PAY, T, I, true>), t_flagged.c_str(), grid_for(cap_c, per), T, st, w, c,
+                   kin, pay_in, kout, perm_out, pay_out);
   return 0;
 }
 
