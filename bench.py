@@ -95,7 +95,7 @@ def pass_bytes_per_key(ks: int):
     return {
         "count_l1": ks,                 # read keys
         "scatter_l1": ks + ks + 4,      # read keys; write key + position
-        "count_l2": ks + 4,             # read key + position
+        "count_l2": ks,                 # read keys (positions only for keys tying a splitter key)
         "scatter_l2": 2 * (ks + 4),     # read and write key + position
         "local_sort": 2 * (ks + 4),     # read key + position; write key + perm
     }

@@ -141,6 +141,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev) {
     ct += tt;
     cc += tc;
   }
+  if (threadIdx.x < 16) w.ctl->queue[threadIdx.x >> 3][threadIdx.x & 7] = 0;
   if (threadIdx.x == 0) {
     w.group_base[m] = ct;
     w.count_base[m] = cc;
@@ -287,19 +288,33 @@ __device__ __forceinline__ uint32_t find_seg(const uint32_t* base, uint32_t m, u
   return lo;
 }
 
-// XCD-aware order of tile groups: workgroups are dispatched round-robin over
-// the 8 XCDs, so workgroup g runs on XCD g % 8.  Each XCD owns a contiguous
-// range of groups and each of its workgroups a contiguous sub-range:
-// neighbouring groups write neighbouring parts of each bucket's output run
-// (which then meet in the same L2), and consecutive groups of a workgroup
-// mostly belong to the same segment, whose splitter tree then stays in LDS.
-struct GroupWalk {
-  uint32_t next, end;
-  __device__ __forceinline__ GroupWalk(uint32_t G) {
-    const uint32_t x = blockIdx.x & 7u, r = blockIdx.x >> 3, per = max(gridDim.x >> 3, 1u);
-    const uint64_t lo = ((uint64_t)G * x) >> 3, hi = ((uint64_t)G * (x + 1)) >> 3;
-    next = (uint32_t)(lo + (hi - lo) * r / per);
-    end = (uint32_t)(lo + (hi - lo) * (r + 1) / per);
+// Work queue of tile groups, XCD-aware: workgroups are dispatched round-robin
+// over the 8 XCDs, so workgroup g runs on XCD g % 8.  Each XCD owns a
+// contiguous share of the groups, and its workgroups take the next group of
+// that share from the XCD's own counter: neighbouring groups write
+// neighbouring parts of each bucket's output run (which then meet in the same
+// L2), consecutive groups of a workgroup mostly belong to the same segment
+// (whose splitter tree then stays in LDS), and a workgroup that finishes
+// early takes more, so uneven segments do not leave a tail of idle CUs.
+struct GroupQueue {
+  uint32_t* ctr;
+  uint32_t lo, hi;
+  __device__ __forceinline__ GroupQueue(uint32_t* q, uint32_t G) {
+    const uint32_t x = blockIdx.x & 7u;
+    lo = (uint32_t)(((uint64_t)G * x) >> 3);
+    hi = (uint32_t)(((uint64_t)G * (x + 1)) >> 3);
+    ctr = q + x;
+  }
+  // Called by every thread; returns the next group, or hi when the share is
+  // done.  The caller's group loop must pass a __syncthreads before the next
+  // call (slot is rewritten there).
+  __device__ __forceinline__ uint32_t next(uint32_t* slot) {
+    if (threadIdx.x == 0) {
+      const uint32_t g = lo + atomicAdd(ctr, 1u);
+      *slot = g < hi ? g : hi;
+    }
+    __syncthreads();
+    return *slot;
   }
 };
 
@@ -362,8 +377,9 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
   }
   for (uint32_t i = threadIdx.x; i < kMaxK; i += THREADS) hist[i] = 0;
   __syncthreads();
-  for (GroupWalk gw(G); gw.next < gw.end; gw.next++) {
-    const uint32_t group = gw.next;
+  __shared__ uint32_t s_group;
+  GroupQueue gq(w.ctl->queue[0], G);
+  for (uint32_t group = gq.next(&s_group); group < gq.hi; group = gq.next(&s_group)) {
     seg_for_group<K, THREADS>(w, cur, m, group, sc, tk, ti, false);
     const uint32_t gl = group - sc.gb;
     const uint32_t nt = (sc.len + TILE - 1) / TILE;
@@ -519,8 +535,9 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
   if (threadIdx.x < kMaxK) hist[threadIdx.x] = 0;
   __syncthreads();
 
-  for (GroupWalk gw(G); gw.next < gw.end; gw.next++) {
-    const uint32_t group = gw.next;
+  __shared__ uint32_t s_group;
+  GroupQueue gq(w.ctl->queue[1], G);
+  for (uint32_t group = gq.next(&s_group); group < gq.hi; group = gq.next(&s_group)) {
     seg_for_group<K, THREADS>(w, cur, m, group, sc, tk, ti, true);
     const uint32_t gl = group - sc.gb;
     const uint32_t ng = sc.gb_end - sc.gb;
@@ -841,8 +858,9 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
     // count tiles: 512 threads x 8 keys; scatter tiles: 512 x 8 (tile_log2
     // 12) or 1024 x 8 (tile_log2 13); both walk the same groups of
     // kGroupKeys keys.  Grids are multiples of 8 for the XCD-aware walk.
-    const uint32_t gt = std::max<uint32_t>(8u, grid_for(groups_max, 8) & ~7u);
-    const uint32_t gs_sc = std::max<uint32_t>(8u, grid_for(groups_max, tile_log2 == 12 ? 8 : 4) & ~7u);
+    // resident-sized grids: the workgroups take groups from the queues
+    const uint32_t gt = std::max<uint32_t>(8u, grid_for(groups_max, 4) & ~7u);
+    const uint32_t gs_sc = std::max<uint32_t>(8u, grid_for(groups_max, tile_log2 == 12 ? 2 : 1) & ~7u);
     if (lev == 0)
       RS_LAUNCH((k_count<K, F32, true, 512, 8>), gt, 512, st, w, (int)lev, kin, src);
     else

@@ -41,6 +41,7 @@ struct Ctl {
   uint32_t big_count[2];           // ping-pong lists of segments to split
   uint32_t total_groups;           // tile groups of the current level
   uint32_t total_counts;           // entries of the current level's count matrix
+  uint32_t queue[2][8];            // per-XCD tile-group queues of the count and scatter passes
   uint32_t class_count[kNumClasses];  // final segments per size class (last = oversize)
   uint32_t level_max[kMaxLevels];  // largest bucket created per level
   uint32_t level_buckets[kMaxLevels];
