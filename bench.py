@@ -324,21 +324,22 @@ def bench_latency(args, R, torch):
 
     n = 1 << 20
     x = torch.from_numpy(gen.keys("u64", "uniform", n, seed=1)).cuda()
-    ws = torch.empty(R.plain_workspace_bytes(R.U64, n), dtype=torch.uint8, device="cuda")
     ko = torch.empty_like(x)
     po = torch.empty(n, dtype=torch.uint32, device="cuda")
-    for _ in range(max(args.warmup, 3)):
-        R.sort(x, workspace=ws, out=(ko, po))
-    torch.cuda.synchronize()
-    st = R.stats(ws)
     us = []
-    for _ in range(max(args.steps, 20)):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        R.sort(x, workspace=ws, out=(ko, po))
-        b.record()
-        b.synchronize()
-        us.append(a.elapsed_time(b) * 1e3)
+    with R.tuned(target=4096):  # one level of 256 buckets of about 4096 keys
+        ws = torch.empty(R.plain_workspace_bytes(R.U64, n), dtype=torch.uint8, device="cuda")
+        for _ in range(max(args.warmup, 3)):
+            R.sort(x, workspace=ws, out=(ko, po))
+        torch.cuda.synchronize()
+        st = R.stats(ws)
+        for _ in range(max(args.steps, 20)):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            R.sort(x, workspace=ws, out=(ko, po))
+            b.record()
+            b.synchronize()
+            us.append(a.elapsed_time(b) * 1e3)
     us = np.array(us)
     mean = float(us.mean())
     return {"metric": "us per plain sort of 2^20 u64 keys (latency)", "value": round(mean, 2), "unit": "us",
@@ -346,7 +347,7 @@ def bench_latency(args, R, torch):
             "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
             "data": "synthetic",
             "config": {"workload": "plain sort of 2^20 uniform uint64 keys (seed 1), single level of 256 buckets",
-                       "n": n, "levels": int(st["levels"])},
+                       "n": n, "levels": int(st["levels"]), "buckets": int(st["k"])},
             "p50_us": round(float(np.percentile(us, 50)), 2), "min_us": round(float(us.min()), 2),
             "gkeys_per_s": round(n / mean / 1e3, 3)}
 

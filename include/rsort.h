@@ -112,7 +112,7 @@ int rsort_workspace_status(const void *workspace, void *stream);
  * sample elements chosen, as (ord key, position) pairs; keys are u64 holding
  * the ordinal key -- for f32 keys the totalOrder bits) and the sizes of its
  * buckets.  Host output arrays:
- *   spl_keys[255], spl_pos[255], bucket_sizes[256]; *num_buckets receives the
+ *   spl_keys[511], spl_pos[511], bucket_sizes[512]; *num_buckets receives the
  *   bucket count k (0 if no split happened), *levels the number of levels
  *   enqueued, level_max[8] the largest bucket produced per level and
  *   level_buckets[8] the number of non-empty buckets per level, *oversize the

@@ -43,9 +43,18 @@ __device__ __forceinline__ uint32_t class_of(uint32_t len, uint32_t cap, uint32_
   return c;
 }
 
-__device__ __forceinline__ uint32_t logk_for(uint32_t len, uint32_t target) {
-  uint32_t q = (len + target - 1) / target;  // buckets wanted
-  uint32_t lk = q <= 1 ? 1u : 32u - __clz(q - 1);
+// log2 of the bucket count for a segment of len keys that still has `left`
+// levels (this one included) to reach buckets of about `target` keys: the
+// 2^lq buckets needed are shared out over the levels the segment needs, the
+// upper levels taking the smaller share (fewer buckets where the data is
+// largest keeps the scatter's runs long).
+__device__ __forceinline__ uint32_t logk_for(uint32_t len, uint32_t target, uint32_t left) {
+  const uint32_t q = (len + target - 1) / target;  // buckets wanted
+  const uint32_t lq = q <= 1 ? 0u : 32u - __clz(q - 1);
+  const uint32_t need = (lq + kMaxLogK - 1) / kMaxLogK;
+  const uint32_t lv = left < need ? left : (need ? need : 1u);
+  uint32_t lk = lv > 1 ? lq / lv : lq;
+  lk = lk < 1u ? 1u : lk;
   return lk > (uint32_t)kMaxLogK ? (uint32_t)kMaxLogK : lk;
 }
 
@@ -56,12 +65,12 @@ __device__ __forceinline__ void set_status(Ctl* ctl, int32_t code) { atomicCAS(&
 // aggregated; every lane of the wave must call it.
 __device__ __forceinline__ void route(const Work& w, uint32_t* big_counter, BigSeg* big_list, bool active,
                                       bool to_big, uint64_t start, uint64_t ubase, uint32_t len, uint32_t src,
-                                      uint32_t cap, uint32_t ff, uint32_t target) {
+                                      uint32_t cap, uint32_t ff, uint32_t target, uint32_t left) {
   const bool ab = active && to_big, af = active && !to_big;
   const uint32_t i = wave_append(big_counter, 0u, ab);
   if (ab) {
     if (i < w.big_max)
-      big_list[i] = BigSeg{start, ubase, len, logk_for(len, target)};
+      big_list[i] = BigSeg{start, ubase, len, logk_for(len, target, left)};
     else
       set_status(w.ctl, -3);  // capacity bound violated: internal error
   }
@@ -112,7 +121,8 @@ __global__ void k_init(Work w, const uint64_t* seg_off, uint32_t num_segs, uint6
     }
     const uint32_t len = active ? (uint32_t)(b - a) : 0u;
     active = active && len > 0;
-    route(w, &w.ctl->big_count[0], w.big[0], active, len > cap && levels > 0, a, a, len, 0u, cap, ff, target);
+    route(w, &w.ctl->big_count[0], w.big[0], active, len > cap && levels > 0, a, a, len, 0u, cap, ff, target,
+          levels);
   }
 }
 
@@ -172,7 +182,9 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
   K* tkey = (K*)w.tree_key;
   for (uint32_t s = blockIdx.x; s < m; s += gridDim.x) {
     const BigSeg bs = w.big[cur][s];
-    const uint32_t S = a << bs.logk;  // <= N by construction
+    // a samples per bucket, fewer when a * k would exceed the LDS sample
+    const uint32_t ae = min(a, (uint32_t)(THREADS * ITEMS) >> bs.logk);
+    const uint32_t S = ae << bs.logk;
     K k[ITEMS];
     uint32_t v[ITEMS], p[ITEMS];
 #pragma unroll
@@ -203,14 +215,14 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
       const uint32_t d = 31u - __clz(node);
       const uint32_t q = node - (1u << d);
       const uint32_t j = (2u * q + 1u) << (bs.logk - 1u - d);
-      const uint32_t r = j * a - 1u;
+      const uint32_t r = j * ae - 1u;
       tkey[(uint64_t)s * kMaxK + node] = sa.key(lpad(r));
       w.tree_idx[(uint64_t)s * kMaxK + node] = s_v[lpad(r)];
     }
     if (lev == 0 && s == 0) {
       for (uint32_t j = threadIdx.x + 1; j < kk; j += THREADS) {
-        w.ctl->l0_spl_key[j - 1] = (uint64_t)sa.key(lpad(j * a - 1u));
-        w.ctl->l0_spl_pos[j - 1] = s_v[lpad(j * a - 1u)];
+        w.ctl->l0_spl_key[j - 1] = (uint64_t)sa.key(lpad(j * ae - 1u));
+        w.ctl->l0_spl_pos[j - 1] = s_v[lpad(j * ae - 1u)];
       }
       if (threadIdx.x == 0) w.ctl->l0_k = kk;
     }
@@ -508,6 +520,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
   constexpr uint32_t GT = kGroupKeys / TILE;  // tiles per group
   static_assert(GT * TILE == kGroupKeys, "tiles divide a group");
   static_assert(THREADS >= kMaxK, "one histogram bin per thread");
+  static_assert(TILE <= (1u << 23), "ranks fit 23 bits");
   __shared__ K tk[kMaxK];
   __shared__ uint32_t ti[kMaxK];
   __shared__ uint32_t hist[kMaxK];
@@ -516,7 +529,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
   __shared__ SegCache sc;
   __shared__ K stage[TILE];
   __shared__ uint32_t stage32[TILE];
-  __shared__ uint8_t stage_b[TILE];
+  __shared__ uint16_t stage_b[TILE];
 
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
@@ -591,7 +604,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
         } else if (valid[i]) {
           r = atomicAdd(&hist[b[i]], 1u);
         }
-        pos[i] = valid[i] ? ((b[i] << 24) | r) : 0xFFFFFFFFu;  // r < TILE <= 2^24
+        pos[i] = valid[i] ? ((b[i] << 23) | r) : 0xFFFFFFFFu;  // b < 2^9, r < TILE <= 2^23
       }
       __syncthreads();
       // exclusive scan of the tile histogram -> tile-local bucket starts
@@ -608,12 +621,12 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         if (pos[i] != 0xFFFFFFFFu) {
-          const uint32_t bb = pos[i] >> 24;
-          const uint32_t p = hist[bb] + (pos[i] & 0xFFFFFFu);
+          const uint32_t bb = pos[i] >> 23;
+          const uint32_t p = hist[bb] + (pos[i] & 0x7FFFFFu);
           pos[i] = p;
           stage[p] = key[i];
           stage32[p] = idx[i];
-          stage_b[p] = (uint8_t)bb;
+          stage_b[p] = (uint16_t)bb;
         }
       }
       __syncthreads();
@@ -638,7 +651,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
 
 // Buckets of the finished level: split again or sort in LDS.
 __global__ void k_level_end(Work w, int lev, uint32_t cap, uint32_t target, int last, uint32_t dst_code,
-                            uint32_t ff) {
+                            uint32_t ff, uint32_t left) {
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
   const uint64_t total = (uint64_t)m * kMaxK;
@@ -677,7 +690,7 @@ __global__ void k_level_end(Work w, int lev, uint32_t cap, uint32_t target, int 
     }
     active = active && len > 0;
     route(w, &w.ctl->big_count[cur ^ 1], w.big[cur ^ 1], active, len > cap && !last, bs.start + lo, bs.ubase, len,
-          dst_code, cap, ff, target);
+          dst_code, cap, ff, target, left);
   }
 }
 
@@ -802,7 +815,7 @@ static inline uint32_t grid_for(uint64_t work, uint32_t per_cu) {
 
 
 
-constexpr int kSplThreads = 1024, kSplItems = 8;  // up to 8192 samples (a = 32, k = 256)
+constexpr int kSplThreads = 1024, kSplItems = 8;  // up to 8192 samples (a = 32 at k = 256, 16 at 512)
 
 // Algorithm of each size class: RFIS, RQuick or the LDS merge sort.
 template <typename K, bool F32, bool PAY>
@@ -881,7 +894,7 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
         RS_LAUNCH((k_scatter<K, false, false, PAY, 1024, 8>), gs_sc, 1024, st, w, (int)lev, kin, pay_in, src, dst);
     }
     RS_LAUNCH(k_level_end, grid_for((w.big_max * kMaxK + 255) / 256, 4), 256, st, w, (int)lev, cap, target,
-              last ? 1 : 0, (uint32_t)(dst + 1), ff);
+              last ? 1 : 0, (uint32_t)(dst + 1), ff, levels - lev - 1);
   }
 
   // final segments by size class (a class can only be non-empty if its lower

@@ -7,7 +7,7 @@
 
 namespace rs {
 
-constexpr int kMaxLogK = 8;               // at most 256 buckets per level
+constexpr int kMaxLogK = 9;               // at most 512 buckets per level
 constexpr int kMaxK = 1 << kMaxLogK;
 constexpr int kMaxLevels = 8;
 constexpr int kNumClasses = 10;           // final-bucket size classes (see the class table in engine.hip)

@@ -214,9 +214,9 @@ def stats(workspace: torch.Tensor, stream=None) -> dict:
     """Diagnostics of the last call that used this workspace (see rsort_stats)."""
     import numpy as np
 
-    sk = np.zeros(255, np.uint64)
-    sp = np.zeros(255, np.uint32)
-    bs = np.zeros(256, np.uint32)
+    sk = np.zeros(511, np.uint64)
+    sp = np.zeros(511, np.uint32)
+    bs = np.zeros(512, np.uint32)
     lm = np.zeros(8, np.uint32)
     lb = np.zeros(8, np.uint32)
     nb, lv, ov = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()

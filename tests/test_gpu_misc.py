@@ -25,7 +25,7 @@ def test_level0_buckets_match_oracle_classification(kt, dist):
                      device="cuda")
     ko, po = R.sort(dev(x), workspace=ws)
     st = R.stats(ws)
-    assert st["status"] == 0 and st["k"] == 256 and st["levels"] >= 1
+    assert st["status"] == 0 and st["k"] >= 2 and st["levels"] >= 1
     sk = st["splitter_keys"]
     if kt == "u64":
         skeys = sk.astype(np.uint64)
@@ -37,7 +37,7 @@ def test_level0_buckets_match_oracle_classification(kt, dist):
             b = xin
             xin = np.where(b >> np.uint32(31) == 1, ~b, b | np.uint32(0x80000000)).astype(np.uint32)
     bucket = O.classify(xin, None, skeys, st["splitter_pos"])
-    hist = np.bincount(bucket, minlength=256)
+    hist = np.bincount(bucket, minlength=st["k"])
     assert np.array_equal(hist, st["bucket_sizes"].astype(np.int64))
     assert st["bucket_sizes"].sum() == n
 
@@ -53,9 +53,11 @@ def test_balance_per_level(dist):
     R.sort(dev(x), workspace=ws)
     st = R.stats(ws)
     assert st["oversize"] == 0
-    avg0 = n / 256
+    k = st["k"]
+    assert k >= 2
+    avg0 = n / k
     assert st["level_max"][0] < 2.5 * avg0
-    assert st["level_buckets"][0] == 256  # no bucket empty: ties split by position
+    assert st["level_buckets"][0] == k  # no bucket empty: ties split by position
 
 
 @pytest.mark.parametrize("tune", [dict(oversample=4), dict(oversample=32), dict(tile_log2=13), dict(cap=4096),

@@ -56,7 +56,7 @@ def test_plain_keys_only_and_empty():
 
 
 def test_config1_uniform_2p20_seed1():
-    """2^20 uniform u64 keys from seed 1 (single level, 256 buckets)."""
+    """2^20 uniform u64 keys from seed 1 (a single sample-sort level)."""
     n = 1 << 20
     x = gen.keys("u64", "uniform", n, seed=1)
     ko, po = gpu_sort(x)
@@ -77,7 +77,7 @@ def test_f32_specials():
 
 @pytest.mark.parametrize("dist", ["uniform", "gaussian", "zero", "deterdupl", "reverse"])
 def test_config2_full_size(dist):
-    """2^28 u64 keys, two levels of 256 buckets: closed forms or the
+    """2^28 u64 keys, two sample-sort levels: closed forms or the
     characterising invariants, plus ranks of sampled outputs computed by the
     oracle one by one."""
     n = 1 << 28
