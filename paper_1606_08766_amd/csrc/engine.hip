@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev) {
     const uint32_t i = base + threadIdx.x;
     uint32_t nt = 0, nc = 0;
     if (i < m) {
-      nt = (B[i].len + kGroupKeys - 1) / kGroupKeys;  // groups
+      nt = (uint32_t)(((uint64_t)B[i].len + (1u << w.group_log2) - 1) >> w.group_log2);  // groups
       nc = nt << B[i].logk;
     }
     uint32_t tt, tc;
@@ -371,8 +371,8 @@ __device__ __forceinline__ void seg_for_group(const Work& w, int cur, uint32_t m
 template <typename K, bool F32, bool SRC_IN, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_keys, int src_buf) {
   constexpr uint32_t TILE = THREADS * ITEMS;
-  constexpr uint32_t GT = kGroupKeys / TILE;  // tiles per group
-  static_assert(GT * TILE == kGroupKeys, "tiles divide a group");
+  static_assert(TILE <= (1u << kGroupMinLog2), "tiles divide a group");
+  const uint32_t GT = (1u << w.group_log2) / TILE;  // tiles per group
   __shared__ K tk[kMaxK];
   __shared__ uint32_t ti[kMaxK];
   __shared__ uint32_t hist[kMaxK];
@@ -517,8 +517,8 @@ template <typename K, bool F32, bool SRC_IN, bool PAY, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* in_keys, const uint32_t* in_pay,
                                                      int src_buf, int dst_buf) {
   constexpr uint32_t TILE = THREADS * ITEMS;
-  constexpr uint32_t GT = kGroupKeys / TILE;  // tiles per group
-  static_assert(GT * TILE == kGroupKeys, "tiles divide a group");
+  static_assert(TILE <= (1u << kGroupMinLog2), "tiles divide a group");
+  const uint32_t GT = (1u << w.group_log2) / TILE;  // tiles per group
   static_assert(THREADS >= kMaxK, "one histogram bin per thread");
   static_assert(TILE <= (1u << 23), "ranks fit 23 bits");
   __shared__ K tk[kMaxK];
@@ -720,6 +720,15 @@ uint32_t effective_cap(const Tuning& t, bool pay) {
   return std::max<uint32_t>(cap, 64u);
 }
 
+// Keys per tile group: about four groups per CU for n keys, so that a level
+// over one segment still fills the GPU, within [2^13, 2^17].
+static uint32_t group_log2_for(uint64_t n) {
+  const uint64_t want = n / ((uint64_t)num_cu_cached() * 4);
+  uint32_t lg = kGroupMinLog2;
+  while (lg < kGroupMaxLog2 && (1ull << (lg + 1)) <= want) lg++;
+  return lg;
+}
+
 // Workspace layout: returns total bytes; fills w (pointers relative to base).
 size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, char* base, Work* w,
               uint32_t* levels_out) {
@@ -727,7 +736,8 @@ size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, 
   const uint32_t cap = effective_cap(t, pay);
   const uint32_t levels = plan_levels(n, t, cap);
   const uint64_t big_max = levels ? n / (cap + 1) + 1 : 0;
-  const uint64_t groups_max = levels ? n / kGroupKeys + big_max + 1 : 0;
+  const uint32_t glog = group_log2_for(n);
+  const uint64_t groups_max = levels ? (n >> glog) + big_max + 1 : 0;
   const uint64_t count_max = groups_max * kMaxK;
   const uint64_t scan_blocks = count_max / kScanChunk + 2;
   const uint64_t final_max = (uint64_t)num_segs + (uint64_t)levels * kMaxK * big_max + 1;
@@ -783,6 +793,7 @@ size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, 
       w->buf_pay[b] = pay ? (uint32_t*)(base + o_bp[b]) : nullptr;
     }
     w->big_max = big_max;
+    w->group_log2 = glog;
     w->count_max = count_max;
     w->scan_blocks = scan_blocks;
     w->n = n;
@@ -855,7 +866,7 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
   RS_LAUNCH(k_init, grid_for((num_segs + 255) / 256, 4), 256, st, w, seg_off, num_segs, n, cap, target, levels, ff);
 
   const uint32_t tile_log2 = t.tile_log2 == 12 ? 12 : 13;
-  const uint64_t groups_max = n / kGroupKeys + w.big_max + 1;
+  const uint64_t groups_max = (n >> w.group_log2) + w.big_max + 1;
   for (uint32_t lev = 0; lev < levels; lev++) {
     const int dst = lev & 1;
     const int src = (lev + 1) & 1;  // buffer written by the previous level
@@ -870,7 +881,7 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
     }
     // count tiles: 512 threads x 8 keys; scatter tiles: 512 x 8 (tile_log2
     // 12) or 1024 x 8 (tile_log2 13); both walk the same groups of
-    // kGroupKeys keys.  Grids are multiples of 8 for the XCD-aware walk.
+    // 2^group_log2 keys.  Grids are multiples of 8 for the XCD-aware walk.
     // resident-sized grids: the workgroups take groups from the queues
     const uint32_t gt = std::max<uint32_t>(8u, grid_for(groups_max, 4) & ~7u);
     const uint32_t gs_sc = std::max<uint32_t>(8u, grid_for(groups_max, tile_log2 == 12 ? 2 : 1) & ~7u);

@@ -12,10 +12,12 @@ constexpr int kMaxK = 1 << kMaxLogK;
 constexpr int kMaxLevels = 8;
 constexpr int kNumClasses = 10;           // final-bucket size classes (see the class table in engine.hip)
 constexpr uint32_t kMaxOversample = 32;
-// A segment's keys are handled in aligned groups of kGroupKeys keys, each by
-// one workgroup; histograms and offsets are kept per (bucket, group), so the
-// count and scatter passes may use different tile sizes inside a group.
-constexpr uint32_t kGroupKeys = 1u << 17;
+// A segment's keys are handled in aligned groups of 2^group_log2 keys (a
+// power of two between kGroupMinLog2 and kGroupMaxLog2, chosen per call so
+// that the groups of n keys occupy the whole GPU), each by one workgroup;
+// histograms and offsets are kept per (bucket, group), so the count and
+// scatter passes may use different tile sizes inside a group.
+constexpr uint32_t kGroupMinLog2 = 13, kGroupMaxLog2 = 17;
 
 // A segment that the current level splits.
 struct BigSeg {
@@ -71,6 +73,7 @@ struct Work {
   uint32_t* buf_idx[2];  // [n]
   uint32_t* buf_pay[2];  // [n] (payload calls only)
   uint64_t big_max, count_max, scan_blocks, n;
+  uint32_t group_log2;   // log2 of the keys per tile group
 };
 
 // Launcher flag (or-ed into the class index): sort the whole input of a

@@ -120,12 +120,12 @@ __device__ __forceinline__ void block_minmax(K& mn, K& mx, K* red) {
 //   exact words   rb + 32 (+ PB with payload) <= 64: the word
 //                 (key - mn, position [, slot]) orders exactly like the
 //                 (key, position) pair;
-//   slot words    rb + PB <= 64: the word (key - mn, slot); equal keys then
-//                 come out in slot order, which is checked against their
-//                 positions afterwards.
-// A segment that fits neither, or whose check finds equal keys out of
-// position order, is marked kPairsFlag and sorted by k_local_sort<FLAGGED>
-// launched next.  Every path produces the same output; words take half the
+//   slot words    otherwise: the word (top 64 - PB bits of key - mn, slot);
+//                 words with equal top parts (equal keys, or keys differing
+//                 only in dropped low bits) come out in slot order, which is
+//                 checked against their (key, position) order afterwards.
+// A segment whose check finds such a pair out of order is marked kPairsFlag
+// and sorted by k_local_sort<FLAGGED> launched next.  Every path produces the same output; words take half the
 // LDS of pairs and one compare per merge step.
 template <typename K, bool F32, bool PAY, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const K* in_keys, const uint32_t* in_pay,
@@ -149,6 +149,7 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
     const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
     const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
     auto idx_at = [&](uint32_t j) -> uint32_t { return f.src ? srci[f.start + j] : j; };
+    auto key_at = [&](uint32_t j) -> K { return f.src ? srck[f.start + j] : load_ord<K, F32>(srck, f.start + j); };
     // thread t takes slots i*THREADS+t (striped, coalesced)
     K k[ITEMS];
     K mn = KMax<K>::v, mx = K(0);
@@ -165,10 +166,12 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
     const uint64_t range = (uint64_t)(mx - mn);
     const int rb = range ? 64 - __clzll((long long)range) : 0;
     const bool exact = rb + 32 + XB <= 64;
-    if (!exact && rb + PB > 64) {
-      if (threadIdx.x == 0) w.cls[cls][q].src = f.src | kPairsFlag;
-      continue;  // uniform
-    }
+    // slot words keep the top 64 - PB bits of (key - mn): drop low bits when
+    // the key range is wider than that
+    const int drop = exact ? 0 : max(rb + PB - 64, 0);
+    // the order of equal word prefixes must be checked unless it is exact: no
+    // key bits dropped and slots in position order (segments of the input)
+    const bool check = !exact && (drop > 0 || f.src != 0);
     const int sh = exact ? 32 + XB : PB;
     uint64_t c[ITEMS];
 #pragma unroll
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
       const uint32_t j = i * THREADS + tid;
       uint64_t low = j;
       if (exact) low = ((uint64_t)(j < f.len ? idx_at(j) : 0u) << XB) | (PAY ? j : 0u);
-      c[i] = j < f.len ? ((uint64_t)(k[i] - mn) << sh) | low : ~0ull;
+      c[i] = j < f.len ? (((uint64_t)(k[i] - mn) >> drop) << sh) | low : ~0ull;
     }
     lds_merge_sort_words<THREADS, ITEMS>(c, s_lo, s_hi, tid);
 #pragma unroll
@@ -192,17 +195,24 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
       const uint64_t cj = ((uint64_t)s_hi[qq] << 32) | s_lo[qq];
       const uint32_t slot = (uint32_t)(cj & SLOT);
       uint32_t idx;
+      K key;
       if (exact) {
         idx = (uint32_t)(cj >> XB);
+        key = (K)(mn + (K)(cj >> sh));
       } else {
         idx = idx_at(slot);
-        if (j + 1 < f.len) {
+        key = drop ? key_at(slot) : (K)(mn + (K)(cj >> sh));
+        if (check && j + 1 < f.len) {
           const int qn = lpad(j + 1);
           const uint64_t cn = ((uint64_t)s_hi[qn] << 32) | s_lo[qn];
-          if ((cn >> PB) == (cj >> PB) && idx_at((uint32_t)(cn & SLOT)) < idx) bad = true;
+          if ((cn >> PB) == (cj >> PB)) {
+            // equal prefixes: the pair order decides
+            const uint32_t sn = (uint32_t)(cn & SLOT);
+            if (pair_less(key_at(sn), idx_at(sn), key, idx)) bad = true;
+          }
         }
       }
-      keys_out[f.start + j] = to_output<K, F32>((K)(mn + (K)(cj >> sh)));
+      keys_out[f.start + j] = to_output<K, F32>(key);
       if (perm_out) perm_out[f.start + j] = idx;
       if constexpr (PAY) pay_out[f.start + j] = srcp[f.start + slot];
     }
