@@ -114,6 +114,117 @@ __device__ __forceinline__ void block_minmax(K& mn, K& mx, K* red) {
 }
 
 // ---------------------------------------------------------------------------
+// Bins of the word sort: a segment's words are distinct, so each word's rank
+// is the number of smaller words.  The words are first distributed into 2^LB
+// bins by the top bits of (word - smallest word), which keeps the bins in word
+// order; a word's rank is then the start of its bin plus the number of smaller
+// words inside the bin, found by comparing against the bin's words only.  On
+// the key distributions the sample sort leaves in a final segment (near
+// uniform over its range) a bin holds about 8 to 16 words, so this takes far
+// fewer steps than a merge sort's log2(len) rounds.  Skewed segments, where a
+// bin would hold more than kBinLimit words, are left to the merge sort.
+constexpr uint32_t kBinLimit = 128;
+
+// Bin phase: c holds the element words, element j = i * THREADS + t as c[i];
+// elements j >= len are not used.  Counts the words of each bin (r receives
+// each word's place among its bin's words, in no particular order), turns the
+// counts into bin starts (bin[S] = len) and returns, uniformly over the block,
+// whether every bin holds at most kBinLimit words.
+template <int THREADS, int ITEMS, int LB>
+__device__ __forceinline__ bool bin_count(const uint64_t (&c)[ITEMS], uint32_t len, uint32_t* bin, uint32_t* tmp,
+                                          uint64_t* red, int t, uint64_t& wmn, int& shift, uint32_t (&r)[ITEMS]) {
+  constexpr int S = 1 << LB;
+  constexpr int SPT = (S + THREADS - 1) / THREADS;  // bins scanned per thread
+  uint64_t wmx = 0;
+  wmn = ~0ull;
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    if ((uint32_t)(i * THREADS + t) < len) {
+      wmn = c[i] < wmn ? c[i] : wmn;
+      wmx = c[i] > wmx ? c[i] : wmx;
+    }
+  }
+  for (int b = t; b <= S; b += THREADS) bin[b] = 0;
+  block_minmax<uint64_t, THREADS>(wmn, wmx, red);
+  const uint64_t range = wmx - wmn;
+  const int bits = range ? 64 - __clzll((long long)range) : 0;
+  shift = bits > LB ? bits - LB : 0;
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    r[i] = 0;
+    if ((uint32_t)(i * THREADS + t) < len) r[i] = atomicAdd(&bin[(uint32_t)((c[i] - wmn) >> shift)], 1u);
+  }
+  __syncthreads();
+  uint32_t loc[SPT], sum = 0;
+  bool over = false;
+#pragma unroll
+  for (int s = 0; s < SPT; s++) {
+    const int b = t * SPT + s;
+    loc[s] = b < S ? bin[b] : 0u;
+    over = over | (loc[s] > kBinLimit);
+    sum += loc[s];
+  }
+  uint32_t e = block_excl_scan<THREADS>(sum, tmp, nullptr);
+#pragma unroll
+  for (int s = 0; s < SPT; s++) {
+    const int b = t * SPT + s;
+    if (b < S) bin[b] = e;
+    e += loc[s];
+  }
+  if (t == 0) bin[S] = len;
+  return !__syncthreads_or(over);
+}
+
+// Rank phase, after bin_count succeeded: places the words in their bins (in
+// wb, unpadded), ranks every word and writes the sorted words to lo/hi at
+// lpad(rank); wb and lo/hi are the same LDS memory, and the caller
+// synchronises before reading lo/hi.  wb holds at least len + 3 words (ranking
+// reads up to three words past a bin's end; the three words past len are set
+// to all ones, larger than any word).
+template <int THREADS, int ITEMS, int LB>
+__device__ __forceinline__ void bin_rank(const uint64_t (&c)[ITEMS], const uint32_t (&r)[ITEMS], uint32_t len,
+                                         uint64_t* wb, uint32_t* lo, uint32_t* hi, const uint32_t* bin, int t,
+                                         uint64_t wmn, int shift) {
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    if ((uint32_t)(i * THREADS + t) < len) wb[bin[(uint32_t)((c[i] - wmn) >> shift)] + r[i]] = c[i];
+  }
+  if (t < 3) wb[len + t] = ~0ull;
+  __syncthreads();
+  // rank of the word at each position: words of later bins and the all-ones
+  // words are larger, so the count may run past the bin's end
+  uint32_t rk[ITEMS];
+  uint64_t wv[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    const uint32_t p = i * THREADS + t;  // < N: inside wb
+    const uint64_t w = wb[p];
+    uint32_t db = (uint32_t)((w - wmn) >> shift);
+    db = p < len ? db : 0u;
+    const uint32_t s0 = bin[db];
+    const uint32_t s1 = p < len ? bin[db + 1] : s0;
+    uint32_t less = 0;
+    for (uint32_t q = s0; q < s1; q += 4) {
+      less += wb[q] < w ? 1u : 0u;
+      less += wb[q + 1] < w ? 1u : 0u;
+      less += wb[q + 2] < w ? 1u : 0u;
+      less += wb[q + 3] < w ? 1u : 0u;
+    }
+    rk[i] = s0 + less;
+    wv[i] = w;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    if ((uint32_t)(i * THREADS + t) < len) {
+      const int qq = lpad((int)rk[i]);
+      lo[qq] = (uint32_t)wv[i];
+      hi[qq] = (uint32_t)(wv[i] >> 32);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Final segments of one size class sorted as single 64-bit words.  With mn the
 // segment's smallest key and rb the bit width of (largest key - mn), and PB
 // the bit width of a slot (the element's place in the segment as stored):
@@ -124,9 +235,12 @@ __device__ __forceinline__ void block_minmax(K& mn, K& mx, K* red) {
 //                 words with equal top parts (equal keys, or keys differing
 //                 only in dropped low bits) come out in slot order, which is
 //                 checked against their (key, position) order afterwards.
-// A segment whose check finds such a pair out of order is marked kPairsFlag
-// and sorted by k_local_sort<FLAGGED> launched next.  Every path produces the same output; words take half the
-// LDS of pairs and one compare per merge step.
+// The words are distinct.  Segments of at least 1024 elements are ordered by
+// bins and ranks (bin_count, bin_rank) unless a bin is too full; the others,
+// and those, by the LDS merge sort of words.  A segment whose check finds a
+// pair out of order is marked kPairsFlag and sorted by k_local_sort<FLAGGED>
+// launched next.  Every path produces the same output; words take half the
+// LDS of pairs and one compare per step.
 template <typename K, bool F32, bool PAY, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const K* in_keys, const uint32_t* in_pay,
                                                          K* keys_out, uint32_t* perm_out, uint32_t* pay_out) {
@@ -135,9 +249,22 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
   constexpr int PB = 32 - __builtin_clz((unsigned)(N - 1));
   constexpr uint64_t SLOT = (1ull << PB) - 1;
   constexpr int XB = PAY ? PB : 0;  // slot bits kept in exact words (payload gather)
-  __shared__ uint32_t s_lo[NP];
-  __shared__ uint32_t s_hi[NP];
+  // bins: about eight words each, for segments long enough to need them
+  constexpr bool BINS = N >= 1024;
+  constexpr int LB = 31 - __builtin_clz((unsigned)(N / 8));
+  // the merge sort and the output read words as two halves (lo, hi); the
+  // bins see the same memory as whole words
+  __shared__ uint64_t s_words[NP];
+  uint32_t* const s_lo = (uint32_t*)s_words;
+  uint32_t* const s_hi = s_lo + NP;
   __shared__ K s_red[2 * (THREADS / kWave)];
+  __shared__ uint64_t s_wred[BINS ? 2 * (THREADS / kWave) : 1];
+  __shared__ uint32_t s_bin[BINS ? (1 << LB) + 1 : 1];
+  __shared__ uint32_t s_tmp[THREADS / kWave + 1];
+  // positions of the segment's elements by slot (for segments of a buffer),
+  // loaded coalesced with the keys
+  __shared__ uint32_t s_idx[N];
+  static_assert(!BINS || NP >= N + 3, "room for the words read past a bin's end");
   const uint32_t cnt_c = final_count(w, cls);
   for (uint32_t q = blockIdx.x; q < cnt_c; q += gridDim.x) {
     const FinalSeg f = final_at(w, cls, q);
@@ -148,16 +275,24 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
     const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
     const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
     const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
-    auto idx_at = [&](uint32_t j) -> uint32_t { return f.src ? srci[f.start + j] : j; };
+    auto idx_at = [&](uint32_t j) -> uint32_t { return f.src ? s_idx[j] : j; };
     auto key_at = [&](uint32_t j) -> K { return f.src ? srck[f.start + j] : load_ord<K, F32>(srck, f.start + j); };
     // thread t takes slots i*THREADS+t (striped, coalesced)
     K k[ITEMS];
+    uint32_t v[ITEMS];
     K mn = KMax<K>::v, mx = K(0);
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = i * THREADS + tid;
+      v[i] = j;
       if (j < f.len) {
-        k[i] = f.src ? srck[f.start + j] : load_ord<K, F32>(srck, f.start + j);
+        if (f.src) {
+          k[i] = srck[f.start + j];
+          v[i] = srci[f.start + j];
+          s_idx[j] = v[i];
+        } else {
+          k[i] = load_ord<K, F32>(srck, f.start + j);
+        }
         mn = k[i] < mn ? k[i] : mn;
         mx = k[i] > mx ? k[i] : mx;
       }
@@ -178,15 +313,24 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = i * THREADS + tid;
       uint64_t low = j;
-      if (exact) low = ((uint64_t)(j < f.len ? idx_at(j) : 0u) << XB) | (PAY ? j : 0u);
+      if (exact) low = ((uint64_t)(j < f.len ? v[i] : 0u) << XB) | (PAY ? j : 0u);
       c[i] = j < f.len ? (((uint64_t)(k[i] - mn) >> drop) << sh) | low : ~0ull;
     }
-    lds_merge_sort_words<THREADS, ITEMS>(c, s_lo, s_hi, tid);
+    bool fits = false;
+    uint64_t wmn = 0;
+    int wsh = 0;
+    uint32_t r[ITEMS];
+    if constexpr (BINS) fits = bin_count<THREADS, ITEMS, LB>(c, f.len, s_bin, s_tmp, s_wred, tid, wmn, wsh, r);
+    if (fits) {
+      bin_rank<THREADS, ITEMS, LB>(c, r, f.len, s_words, s_lo, s_hi, s_bin, tid, wmn, wsh);
+    } else {
+      lds_merge_sort_words<THREADS, ITEMS>(c, s_lo, s_hi, tid);
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const int qq = lpad(tid * ITEMS + i);
-      s_lo[qq] = (uint32_t)c[i];
-      s_hi[qq] = (uint32_t)(c[i] >> 32);
+      for (int i = 0; i < ITEMS; i++) {
+        const int qq = lpad(tid * ITEMS + i);
+        s_lo[qq] = (uint32_t)c[i];
+        s_hi[qq] = (uint32_t)(c[i] >> 32);
+      }
     }
     __syncthreads();
     bool bad = false;
