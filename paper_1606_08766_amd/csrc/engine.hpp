@@ -32,9 +32,11 @@ struct FinalSeg {
   uint64_t start;
   uint32_t len;
   uint32_t src;  // low byte: 0 caller input (positions implicit), 1 buffer A, 2 buffer B;
-                 // kPairsFlag: handed from the word sort to the pair sort
+                 // kPairsFlag: handed from the word sort to the pair sort;
+                 // kMergeFlag: handed from the binned word sort to the merged one
 };
 constexpr uint32_t kPairsFlag = 0x100;
+constexpr uint32_t kMergeFlag = 0x200;
 
 // Control block at the start of the workspace (all counters device-side).
 struct Ctl {

@@ -236,12 +236,13 @@ __device__ __forceinline__ void bin_rank(const uint64_t (&c)[ITEMS], const uint3
 //                 only in dropped low bits) come out in slot order, which is
 //                 checked against their (key, position) order afterwards.
 // The words are distinct.  Segments of at least 1024 elements are ordered by
-// bins and ranks (bin_count, bin_rank) unless a bin is too full; the others,
-// and those, by the LDS merge sort of words.  A segment whose check finds a
-// pair out of order is marked kPairsFlag and sorted by k_local_sort<FLAGGED>
-// launched next.  Every path produces the same output; words take half the
-// LDS of pairs and one compare per step.
-template <typename K, bool F32, bool PAY, int THREADS, int ITEMS>
+// bins and ranks (bin_count, bin_rank); a segment where a bin is too full is
+// marked kMergeFlag and left to the MERGE instance launched next, which (like
+// the instances for shorter segments) sorts the words with the LDS merge
+// sort.  A segment whose check finds a pair out of order is marked kPairsFlag
+// and sorted by k_local_sort<FLAGGED> launched last.  Every path produces the
+// same output; words take half the LDS of pairs and one compare per step.
+template <typename K, bool F32, bool PAY, int THREADS, int ITEMS, bool MERGE = false>
 __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const K* in_keys, const uint32_t* in_pay,
                                                          K* keys_out, uint32_t* perm_out, uint32_t* pay_out) {
   constexpr int N = THREADS * ITEMS;
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
   constexpr uint64_t SLOT = (1ull << PB) - 1;
   constexpr int XB = PAY ? PB : 0;  // slot bits kept in exact words (payload gather)
   // bins: about eight words each, for segments long enough to need them
-  constexpr bool BINS = N >= 1024;
+  constexpr bool BINS = !MERGE && N >= 1024;
   constexpr int LB = 31 - __builtin_clz((unsigned)(N / 8));
   // the merge sort and the output read words as two halves (lo, hi); the
   // bins see the same memory as whole words
@@ -267,7 +268,9 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
   static_assert(!BINS || NP >= N + 3, "room for the words read past a bin's end");
   const uint32_t cnt_c = final_count(w, cls);
   for (uint32_t q = blockIdx.x; q < cnt_c; q += gridDim.x) {
-    const FinalSeg f = final_at(w, cls, q);
+    FinalSeg f = final_at(w, cls, q);
+    if (MERGE && !(f.src & kMergeFlag)) continue;  // uniform
+    f.src &= 0xFFu;
     // an opaque copy of the thread index: per-thread addresses are recomputed
     // per segment rather than hoisted out of the loop and kept live
     int tid = threadIdx.x;
@@ -277,24 +280,23 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
     const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
     auto idx_at = [&](uint32_t j) -> uint32_t { return f.src ? s_idx[j] : j; };
     auto key_at = [&](uint32_t j) -> K { return f.src ? srck[f.start + j] : load_ord<K, F32>(srck, f.start + j); };
-    // thread t takes slots i*THREADS+t (striped, coalesced)
-    K k[ITEMS];
-    uint32_t v[ITEMS];
+    // thread t takes slots i*THREADS+t (striped, coalesced); keys wait in the
+    // word memory (not in registers) until the minimum is known
     K mn = KMax<K>::v, mx = K(0);
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = i * THREADS + tid;
-      v[i] = j;
       if (j < f.len) {
+        K key;
         if (f.src) {
-          k[i] = srck[f.start + j];
-          v[i] = srci[f.start + j];
-          s_idx[j] = v[i];
+          key = srck[f.start + j];
+          s_idx[j] = srci[f.start + j];
         } else {
-          k[i] = load_ord<K, F32>(srck, f.start + j);
+          key = load_ord<K, F32>(srck, f.start + j);
         }
-        mn = k[i] < mn ? k[i] : mn;
-        mx = k[i] > mx ? k[i] : mx;
+        s_words[j] = (uint64_t)key;
+        mn = key < mn ? key : mn;
+        mx = key > mx ? key : mx;
       }
     }
     block_minmax<K, THREADS>(mn, mx, s_red);
@@ -313,17 +315,21 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = i * THREADS + tid;
       uint64_t low = j;
-      if (exact) low = ((uint64_t)(j < f.len ? v[i] : 0u) << XB) | (PAY ? j : 0u);
-      c[i] = j < f.len ? (((uint64_t)(k[i] - mn) >> drop) << sh) | low : ~0ull;
+      if (exact) low = ((uint64_t)(j < f.len ? idx_at(j) : 0u) << XB) | (PAY ? j : 0u);
+      c[i] = j < f.len ? (((uint64_t)((K)s_words[j] - mn) >> drop) << sh) | low : ~0ull;
     }
-    bool fits = false;
-    uint64_t wmn = 0;
-    int wsh = 0;
-    uint32_t r[ITEMS];
-    if constexpr (BINS) fits = bin_count<THREADS, ITEMS, LB>(c, f.len, s_bin, s_tmp, s_wred, tid, wmn, wsh, r);
-    if (fits) {
+    if constexpr (BINS) {
+      uint64_t wmn;
+      int wsh;
+      uint32_t r[ITEMS];
+      if (!bin_count<THREADS, ITEMS, LB>(c, f.len, s_bin, s_tmp, s_wred, tid, wmn, wsh, r)) {
+        // uniform; every thread is past its reads of this segment's LDS
+        if (tid == 0) w.cls[cls][q].src = f.src | kMergeFlag;
+        continue;
+      }
       bin_rank<THREADS, ITEMS, LB>(c, r, f.len, s_words, s_lo, s_hi, s_bin, tid, wmn, wsh);
     } else {
+      __syncthreads();  // every key read from the word memory
       lds_merge_sort_words<THREADS, ITEMS>(c, s_lo, s_hi, tid);
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
@@ -495,6 +501,7 @@ static int merge_class_launch(int c, const Work& w, const K* kin, const uint32_t
   static const std::string shape = std::to_string(T) + ", " + std::to_string(I);
   static const std::string t_pairs = "(k_local_sort<K, F32, PAY, " + shape + ">)";
   static const std::string t_words = "(k_local_words<K, F32, PAY, " + shape + ">)";
+  static const std::string t_merge = "(k_local_words<K, F32, PAY, " + shape + ", true>)";
   static const std::string t_flagged = "(k_local_sort<K, F32, PAY, " + shape + ", true>)";
   if (c & kDirect) {
     RS_LAUNCH_TAGGED((k_local_sort<K, F32, PAY, T, I>), t_pairs.c_str(), 1, T, st, w, -1, kin, pay_in, kout,
@@ -505,6 +512,9 @@ static int merge_class_launch(int c, const Work& w, const K* kin, const uint32_t
   // sort of the rare handed-over segments a resident-sized grid
   RS_LAUNCH_TAGGED((k_local_words<K, F32, PAY, T, I>), t_words.c_str(), grid_for(cap_c, RS_WORDS_PER_CU), T, st, w,
                    c, kin, pay_in, kout, perm_out, pay_out);
+  if (T * I >= 1024)  // the binned instance hands skewed segments to the merged one
+    RS_LAUNCH_TAGGED((k_local_words<K, F32, PAY, T, I, true>), t_merge.c_str(), grid_for(cap_c, per), T, st, w, c,
+                     kin, pay_in, kout, perm_out, pay_out);
   RS_LAUNCH_TAGGED((k_local_sort<K, F32, PAY, T, I, true>), t_flagged.c_str(), grid_for(cap_c, per), T, st, w, c,
                    kin, pay_in, kout, perm_out, pay_out);
   return 0;
