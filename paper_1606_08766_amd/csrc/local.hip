@@ -87,30 +87,100 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
 }
 
 // ---------------------------------------------------------------------------
-// Block-wide minimum and maximum (every thread of the block calls).
+// Block-wide minimum and maximum of the keys and of the positions (every
+// thread of the block calls, every lane active).  Lanes of a row of 16 are
+// combined with DPP moves (xor 1, xor 2, then the half-row and row mirrors),
+// the four rows of a wave by lane reads into scalar registers, the waves
+// through LDS (one row of lanes reads the per-wave values).  The results are
+// uniform and live in scalar registers.  red holds 6 * THREADS/64 words.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  return ((uint64_t)dpp_u32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp_u32<CTRL>((uint32_t)v);
+}
+__device__ __forceinline__ uint32_t lane_u32(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int l) {
+  return ((uint64_t)lane_u32((uint32_t)(v >> 32), l) << 32) | lane_u32((uint32_t)v, l);
+}
+struct Range4 {  // key minimum and maximum (as 64 bits), position minimum and maximum
+  uint64_t kmn, kmx;
+  uint32_t imn, imx;
+};
+
+template <typename K>
+__device__ __forceinline__ void row_reduce(K& kmn, K& kmx, uint32_t& imn, uint32_t& imx) {
+  auto step = [&](auto ctrl) {
+    constexpr int C = decltype(ctrl)::value;
+    K a, b;
+    if constexpr (sizeof(K) == 8) {
+      a = (K)dpp_u64<C>((uint64_t)kmn);
+      b = (K)dpp_u64<C>((uint64_t)kmx);
+    } else {
+      a = (K)dpp_u32<C>((uint32_t)kmn);
+      b = (K)dpp_u32<C>((uint32_t)kmx);
+    }
+    const uint32_t c = dpp_u32<C>(imn), d = dpp_u32<C>(imx);
+    kmn = a < kmn ? a : kmn;
+    kmx = b > kmx ? b : kmx;
+    imn = min(imn, c);
+    imx = max(imx, d);
+  };
+  step(std::integral_constant<int, 0xB1>{});   // quad_perm [1,0,3,2]
+  step(std::integral_constant<int, 0x4E>{});   // quad_perm [2,3,0,1]
+  step(std::integral_constant<int, 0x141>{});  // row_half_mirror
+  step(std::integral_constant<int, 0x140>{});  // row_mirror
+}
+
+template <typename K>
+__device__ __forceinline__ Range4 rows_to_scalar(K kmn, K kmx, uint32_t imn, uint32_t imx, int rows) {
+  Range4 r{~0ull, 0ull, ~0u, 0u};
+  for (int q = 0; q < rows; q++) {
+    uint64_t a, b;
+    if constexpr (sizeof(K) == 8) {
+      a = lane_u64((uint64_t)kmn, 16 * q);
+      b = lane_u64((uint64_t)kmx, 16 * q);
+    } else {
+      a = lane_u32((uint32_t)kmn, 16 * q);
+      b = lane_u32((uint32_t)kmx, 16 * q);
+    }
+    const uint32_t c = lane_u32(imn, 16 * q), d = lane_u32(imx, 16 * q);
+    r.kmn = a < r.kmn ? a : r.kmn;
+    r.kmx = b > r.kmx ? b : r.kmx;
+    r.imn = min(r.imn, c);
+    r.imx = max(r.imx, d);
+  }
+  return r;
+}
+
 template <typename K, int THREADS>
-__device__ __forceinline__ void block_minmax(K& mn, K& mx, K* red) {
+__device__ __forceinline__ Range4 block_range(K kmn, K kmx, uint32_t imn, uint32_t imx, uint32_t* red, int t) {
   constexpr int NW = THREADS / kWave;
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    const K a = __shfl_xor(mn, o, kWave), b = __shfl_xor(mx, o, kWave);
-    mn = a < mn ? a : mn;
-    mx = b > mx ? b : mx;
-  }
-  const int wv = threadIdx.x / kWave;
-  if (lane_id() == 0) {
-    red[wv] = mn;
-    red[NW + wv] = mx;
-  }
-  __syncthreads();
-  mn = red[0];
-  mx = red[NW];
-#pragma unroll
-  for (int i = 1; i < NW; i++) {
-    mn = red[i] < mn ? red[i] : mn;
-    mx = red[NW + i] > mx ? red[NW + i] : mx;
+  static_assert(NW <= 16, "per-wave values fit one row");
+  row_reduce<K>(kmn, kmx, imn, imx);
+  const Range4 wv = rows_to_scalar<K>(kmn, kmx, imn, imx, 4);
+  const int w = t / kWave, lane = t % kWave;
+  if (lane == 0) {
+    red[6 * w + 0] = (uint32_t)wv.kmn;
+    red[6 * w + 1] = (uint32_t)(wv.kmn >> 32);
+    red[6 * w + 2] = (uint32_t)wv.kmx;
+    red[6 * w + 3] = (uint32_t)(wv.kmx >> 32);
+    red[6 * w + 4] = wv.imn;
+    red[6 * w + 5] = wv.imx;
   }
   __syncthreads();
+  K a = KMax<K>::v, b = K(0);
+  uint32_t c = ~0u, d = 0u;
+  if (lane < NW) {
+    a = (K)(((uint64_t)red[6 * lane + 1] << 32) | red[6 * lane + 0]);
+    b = (K)(((uint64_t)red[6 * lane + 3] << 32) | red[6 * lane + 2]);
+    c = red[6 * lane + 4];
+    d = red[6 * lane + 5];
+  }
+  row_reduce<K>(a, b, c, d);
+  return rows_to_scalar<K>(a, b, c, d, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -126,27 +196,20 @@ __device__ __forceinline__ void block_minmax(K& mn, K& mx, K* red) {
 constexpr uint32_t kBinLimit = 128;
 
 // Bin phase: c holds the element words, element j = i * THREADS + t as c[i];
-// elements j >= len are not used.  Counts the words of each bin (r receives
-// each word's place among its bin's words, in no particular order), turns the
-// counts into bin starts (bin[S] = len) and returns, uniformly over the block,
-// whether every bin holds at most kBinLimit words.
+// elements j >= len are not used; every word lies in [wlo, whi].  Counts the
+// words of each bin (bin[0 .. S] are zero on entry; r receives each word's
+// place among its bin's words, in no particular order), turns the counts into
+// bin starts (bin[S] = len) and
+// returns, uniformly over the block, whether every bin holds at most
+// kBinLimit words.  shift receives the bin shift: a word's bin is
+// (word - wlo) >> shift.
 template <int THREADS, int ITEMS, int LB>
 __device__ __forceinline__ bool bin_count(const uint64_t (&c)[ITEMS], uint32_t len, uint32_t* bin, uint32_t* tmp,
-                                          uint64_t* red, int t, uint64_t& wmn, int& shift, uint32_t (&r)[ITEMS]) {
+                                          int t, uint64_t wlo, uint64_t whi, int& shift, uint32_t (&r)[ITEMS]) {
   constexpr int S = 1 << LB;
   constexpr int SPT = (S + THREADS - 1) / THREADS;  // bins scanned per thread
-  uint64_t wmx = 0;
-  wmn = ~0ull;
-#pragma unroll
-  for (int i = 0; i < ITEMS; i++) {
-    if ((uint32_t)(i * THREADS + t) < len) {
-      wmn = c[i] < wmn ? c[i] : wmn;
-      wmx = c[i] > wmx ? c[i] : wmx;
-    }
-  }
-  for (int b = t; b <= S; b += THREADS) bin[b] = 0;
-  block_minmax<uint64_t, THREADS>(wmn, wmx, red);
-  const uint64_t range = wmx - wmn;
+  const uint64_t wmn = wlo;
+  const uint64_t range = whi - wlo;
   const int bits = range ? 64 - __clzll((long long)range) : 0;
   shift = bits > LB ? bits - LB : 0;
 #pragma unroll
@@ -258,8 +321,7 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
   __shared__ uint64_t s_words[NP];
   uint32_t* const s_lo = (uint32_t*)s_words;
   uint32_t* const s_hi = s_lo + NP;
-  __shared__ K s_red[2 * (THREADS / kWave)];
-  __shared__ uint64_t s_wred[BINS ? 2 * (THREADS / kWave) : 1];
+  __shared__ uint32_t s_red[6 * (THREADS / kWave)];
   __shared__ uint32_t s_bin[BINS ? (1 << LB) + 1 : 1];
   __shared__ uint32_t s_tmp[THREADS / kWave + 1];
   // positions of the segment's elements by slot (for segments of a buffer),
@@ -283,23 +345,38 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
     // thread t takes slots i*THREADS+t (striped, coalesced); keys wait in the
     // word memory (not in registers) until the minimum is known
     K mn = KMax<K>::v, mx = K(0);
+    uint32_t imn = ~0u, imx = 0u;
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = i * THREADS + tid;
       if (j < f.len) {
         K key;
+        uint32_t idx = j;
         if (f.src) {
           key = srck[f.start + j];
-          s_idx[j] = srci[f.start + j];
+          idx = srci[f.start + j];
+          s_idx[j] = idx;
         } else {
           key = load_ord<K, F32>(srck, f.start + j);
         }
         s_words[j] = (uint64_t)key;
         mn = key < mn ? key : mn;
         mx = key > mx ? key : mx;
+        imn = min(imn, idx);
+        imx = max(imx, idx);
       }
     }
-    block_minmax<K, THREADS>(mn, mx, s_red);
+    if constexpr (BINS) {
+      for (int b = tid; b <= (1 << LB); b += THREADS) s_bin[b] = 0;
+    }
+    {
+      // its barrier also orders the stores above before their readers
+      const Range4 br = block_range<K, THREADS>(mn, mx, imn, imx, s_red, tid);
+      mn = (K)br.kmn;
+      mx = (K)br.kmx;
+      imn = br.imn;
+      imx = br.imx;
+    }
     const uint64_t range = (uint64_t)(mx - mn);
     const int rb = range ? 64 - __clzll((long long)range) : 0;
     const bool exact = rb + 32 + XB <= 64;
@@ -319,10 +396,15 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
       c[i] = j < f.len ? (((uint64_t)((K)s_words[j] - mn) >> drop) << sh) | low : ~0ull;
     }
     if constexpr (BINS) {
-      uint64_t wmn;
+      // bounds of the words: exact words are at least (position min) and at
+      // most (key range, position max, all slot bits); slot words lie in
+      // [0, (key range >> drop, len - 1)]
+      const uint64_t wmn = exact ? (uint64_t)imn << XB : 0ull;
+      const uint64_t wmx = exact ? ((uint64_t)range << sh) | ((uint64_t)imx << XB) | (PAY ? SLOT : 0ull)
+                                 : (((uint64_t)range >> drop) << PB) | (uint64_t)(f.len - 1);
       int wsh;
       uint32_t r[ITEMS];
-      if (!bin_count<THREADS, ITEMS, LB>(c, f.len, s_bin, s_tmp, s_wred, tid, wmn, wsh, r)) {
+      if (!bin_count<THREADS, ITEMS, LB>(c, f.len, s_bin, s_tmp, tid, wmn, wmx, wsh, r)) {
         // uniform; every thread is past its reads of this segment's LDS
         if (tid == 0) w.cls[cls][q].src = f.src | kMergeFlag;
         continue;
