@@ -118,7 +118,7 @@ def tune(kt: str = "u64", quick: bool = False, seg_keys: int = 1 << 22, n_plain:
         x = torch.from_numpy(gen.keys(kt, "uniform", n_plain, seed=7)).cuda()
         ws = torch.empty(R.plain_workspace_bytes(ktc, n_plain), dtype=torch.uint8, device="cuda")
         out = (torch.empty_like(x), torch.empty(n_plain, dtype=torch.uint32, device="cuda"))
-        grid = list(itertools.product((12, 13), (16, 32), (2048, 3072, 4096)))
+        grid = list(itertools.product((12, 13), (16, 32), (4096, 5120, 6144)))
         if quick:
             grid = grid[:3]
         level = {}

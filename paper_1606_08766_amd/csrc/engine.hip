@@ -703,10 +703,16 @@ Tuning& tuning() { return g_tuning; }
 
 static inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+// Bucket size the levels aim for: at most half the LDS capacity, so that the
+// spread of bucket sizes around it stays below the capacity.
+static uint32_t effective_target(const Tuning& t, uint32_t cap) {
+  return std::max<uint32_t>(64u, std::min<uint32_t>(t.target, cap / 2));
+}
+
 uint32_t plan_levels(uint64_t n, const Tuning& t, uint32_t cap) {
   if (n <= cap) return 0;
   uint32_t L = 0;
-  uint64_t reach = std::max<uint32_t>(64u, std::min<uint32_t>(t.target, cap / 3));
+  uint64_t reach = effective_target(t, cap);
   while (reach < n) {
     reach <<= kMaxLogK;
     L++;
@@ -852,7 +858,7 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
   const uint32_t cap = effective_cap(t, PAY);
   const uint32_t a = std::min<uint32_t>(std::max<uint32_t>(t.oversample, 1), kMaxOversample);
   const uint32_t ff = t.force_fallback;
-  const uint32_t target = std::max<uint32_t>(64u, std::min<uint32_t>(t.target, cap / 3));
+  const uint32_t target = effective_target(t, cap);
   const K* kin = (const K*)keys_in;
   K* kout = (K*)keys_out;
 

@@ -11,7 +11,7 @@ namespace rs {
 
 struct Tuning {
   uint32_t oversample = 32;   // samples per bucket
-  uint32_t target = 4096;     // bucket size a level aims for
+  uint32_t target = 6144;     // bucket size a level aims for (at most cap / 2)
   uint32_t cap = 12288;       // largest bucket sorted in LDS
   uint32_t max_levels = 4;
   uint32_t rfis_max = 256;    // classes with upper bound <= rfis_max use RFIS
