@@ -425,6 +425,11 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
                                    return bidx[pos];
                                },
                                b);
+      if constexpr (!SRC_IN) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++)
+          if (valid[i]) put_bucket_id(w.ids, sc.start, (uint64_t)tl * TILE + i * THREADS + threadIdx.x, sc.logk, b[i]);
+      }
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         // one atomic per wave when the whole wave falls into one bucket
@@ -560,33 +565,53 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
     // tile's count, so the tiles' runs follow each other in group order
     uint64_t run_off = 0;
     if (threadIdx.x < kk) run_off = sc.start + (uint64_t)(w.offsets[sc.cb + threadIdx.x * ng + gl] - sc.seg0);
-    for (uint32_t tl = gl * GT; tl < t_end; tl++) {
-      const BigSeg bs{sc.start, sc.ubase, sc.len, sc.logk};
+    const BigSeg bs{sc.start, sc.ubase, sc.len, sc.logk};
+    // the group's tiles are loaded one ahead: the loads of tile tl + 1 are in
+    // flight while tile tl is classified, ranked and written
+    K nkey[ITEMS];
+    uint32_t nidx[ITEMS], npay[ITEMS], nb[ITEMS];
+    auto load_tile = [&](uint32_t tl) {
       const uint64_t base = bs.start + (uint64_t)tl * TILE;
       const uint32_t cnt = min(TILE, bs.len - tl * TILE);
-      K key[ITEMS];
-      uint32_t idx[ITEMS], pay[ITEMS], pos[ITEMS];
-      bool valid[ITEMS];
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         const uint32_t jj = i * THREADS + threadIdx.x;
-        valid[i] = jj < cnt;
-        key[i] = K(0);
-        idx[i] = 0;
-        pay[i] = 0;
-        if (valid[i]) {
+        nkey[i] = K(0);
+        nidx[i] = 0;
+        npay[i] = 0;
+        nb[i] = 0;
+        if (jj < cnt) {
           if constexpr (SRC_IN) {
-            key[i] = load_ord<K, F32>(in_keys, base + jj);
-            idx[i] = (uint32_t)(base + jj - bs.ubase);
+            nkey[i] = load_ord<K, F32>(in_keys, base + jj);
+            nidx[i] = (uint32_t)(base + jj - bs.ubase);
           } else {
-            key[i] = bkey[base + jj];
-            idx[i] = bidx[base + jj];
+            nkey[i] = bkey[base + jj];
+            nidx[i] = bidx[base + jj];
+            nb[i] = get_bucket_id(w.ids, bs.start, (uint64_t)tl * TILE + jj, bs.logk);
           }
-          if constexpr (PAY) pay[i] = bpay[base + jj];
+          if constexpr (PAY) npay[i] = bpay[base + jj];
         }
       }
-      uint32_t b[ITEMS];
-      classify_batch<K, ITEMS>(tk, ti, bs.logk, key, valid, [&](int i) -> uint32_t { return idx[i]; }, b);
+    };
+    if (gl * GT < t_end) load_tile(gl * GT);
+    for (uint32_t tl = gl * GT; tl < t_end; tl++) {
+      const uint64_t base = bs.start + (uint64_t)tl * TILE;
+      const uint32_t cnt = min(TILE, bs.len - tl * TILE);
+      K key[ITEMS];
+      uint32_t idx[ITEMS], pay[ITEMS], pos[ITEMS], b[ITEMS];
+      bool valid[ITEMS];
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        valid[i] = i * THREADS + threadIdx.x < cnt;
+        key[i] = nkey[i];
+        idx[i] = nidx[i];
+        pay[i] = npay[i];
+        b[i] = nb[i];
+      }
+      if (tl + 1 < t_end) load_tile(tl + 1);
+      // the first level classifies; later ones read the count pass's ids
+      if constexpr (SRC_IN)
+        classify_batch<K, ITEMS>(tk, ti, bs.logk, key, valid, [&](int i) -> uint32_t { return idx[i]; }, b);
       // rank inside (tile, bucket): one LDS atomic per element, or one per wave
       // when the whole wave falls into a single bucket (skewed inputs)
 #pragma unroll
@@ -631,6 +656,14 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
       }
       __syncthreads();
       if (threadIdx.x < kMaxK) hist[threadIdx.x] = 0;  // ready for the next tile
+      // the next tile's loads complete here, before this tile's stores are
+      // issued: a wait for them after the stores would wait for the stores too
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        asm volatile("" ::"v"(nkey[i]), "v"(nidx[i]));
+        if constexpr (PAY) asm volatile("" ::"v"(npay[i]));
+        if constexpr (!SRC_IN) asm volatile("" ::"v"(nb[i]));
+      }
       for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) {
         const uint64_t g = gdelta[stage_b[p]] + p;
         dkey[g] = stage[p];
@@ -772,6 +805,7 @@ size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, 
     o_cls[c] = take(cls_cap[c] * sizeof(FinalSeg));
   }
   const uint64_t nb = (levels || t.force_fallback) ? n : 0;
+  const uint64_t o_ids = take(levels >= 2 ? 2 * n : 0);
   uint64_t o_bk[2], o_bi[2], o_bp[2];
   for (int b = 0; b < 2; b++) {
     o_bk[b] = take(nb * ks);
@@ -798,6 +832,7 @@ size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, 
       w->buf_idx[b] = (uint32_t*)(base + o_bi[b]);
       w->buf_pay[b] = pay ? (uint32_t*)(base + o_bp[b]) : nullptr;
     }
+    w->ids = levels >= 2 ? (uint8_t*)(base + o_ids) : nullptr;
     w->big_max = big_max;
     w->group_log2 = glog;
     w->count_max = count_max;

@@ -74,9 +74,25 @@ struct Work {
   void* buf_key[2];      // A, B: [n] keys (ordinal)
   uint32_t* buf_idx[2];  // [n]
   uint32_t* buf_pay[2];  // [n] (payload calls only)
+  uint8_t* ids;          // [2 n] bucket of each element of a buffer level (see bucket ids below)
   uint64_t big_max, count_max, scan_blocks, n;
   uint32_t group_log2;   // log2 of the keys per tile group
 };
+
+// Bucket ids of a level that reads a buffer: the count pass stores the
+// bucket of the element at buffer position p of a segment starting at s in
+// the segment's own byte range [2 s, 2 s + 2 len) of ids: one byte at 2 s + (p - s)
+// when the segment has at most 256 buckets, else two at 2 s + 2 (p - s).  The
+// scatter reads them instead of classifying again.
+__device__ __forceinline__ void put_bucket_id(uint8_t* ids, uint64_t s, uint64_t r, uint32_t logk, uint32_t b) {
+  if (logk <= 8)
+    ids[2 * s + r] = (uint8_t)b;
+  else
+    ((uint16_t*)(ids + 2 * s))[r] = (uint16_t)b;
+}
+__device__ __forceinline__ uint32_t get_bucket_id(const uint8_t* ids, uint64_t s, uint64_t r, uint32_t logk) {
+  return logk <= 8 ? (uint32_t)ids[2 * s + r] : (uint32_t)((const uint16_t*)(ids + 2 * s))[r];
+}
 
 // Launcher flag (or-ed into the class index): sort the whole input of a
 // plain call as one segment in a single launch.  The kernels then receive a
