@@ -90,13 +90,14 @@ def kernel_class(name: str) -> str:
 
 
 def pass_bytes_per_key(ks: int):
-    """Algorithmic HBM bytes per key of each pass (read + write), u64 keys,
-    u32 positions: see the design doc."""
+    """Algorithmic HBM bytes per key of each pass (read + write) for keys of
+    ks bytes, u32 positions and levels of at most 256 buckets (one-byte
+    bucket ids between the second level's count and scatter)."""
     return {
         "count_l1": ks,                 # read keys
         "scatter_l1": ks + ks + 4,      # read keys; write key + position
-        "count_l2": ks,                 # read keys (positions only for keys tying a splitter key)
-        "scatter_l2": 2 * (ks + 4),     # read and write key + position
+        "count_l2": ks + 1,             # read keys (positions only for keys tying a splitter key); write bucket id
+        "scatter_l2": 2 * (ks + 4) + 1,  # read key + position + bucket id; write key + position
         "local_sort": 2 * (ks + 4),     # read key + position; write key + perm
     }
 
@@ -608,8 +609,8 @@ def main():
                       "rocprofv3 --kernel-trace --stats summary")
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this sort's multi-GPU path is a design, not a build "
-              "(see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the sort is built and measured on a single GPU and its "
+              "sharding over several GPUs is described, not implemented; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
 
