@@ -72,38 +72,43 @@ __device__ __forceinline__ uint64_t rand_at(uint64_t seed, uint64_t stream, uint
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-// Inclusive scan across the 64 lanes of a wave.
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+// Inclusive scan across the 64 lanes of a wave (T: 32- or 64-bit unsigned).
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
   const uint32_t lane = lane_id();
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) {
-    uint32_t o = __shfl_up(v, d, kWave);
+    T o = __shfl_up(v, d, kWave);
     if (lane >= (uint32_t)d) v += o;
   }
   return v;
 }
 
 // Exclusive block scan of one value per thread.  `tmp` holds >= THREADS/64 + 1
-// words of LDS.  Returns the exclusive prefix; *total receives the block sum.
-template <int THREADS>
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
+// values of LDS.  Returns the exclusive prefix; *total receives the block sum.
+template <typename T>
+struct NoDeduce {
+  using type = T;
+};
+template <int THREADS, typename T = uint32_t>
+__device__ __forceinline__ T block_excl_scan(T v, typename NoDeduce<T>::type* tmp, typename NoDeduce<T>::type* total) {
   constexpr int NW = THREADS / kWave;
   const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
-  uint32_t inc = wave_incl_scan(v);
+  T inc = wave_incl_scan<T>(v);
   if (lane == kWave - 1) tmp[w] = inc;
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t s = 0;
+    T s = 0;
 #pragma unroll
     for (int i = 0; i < NW; i++) {
-      uint32_t t = tmp[i];
+      T t = tmp[i];
       tmp[i] = s;
       s += t;
     }
     tmp[NW] = s;
   }
   __syncthreads();
-  uint32_t r = tmp[w] + inc - v;
+  T r = tmp[w] + inc - v;
   if (total) *total = tmp[NW];
   __syncthreads();
   return r;

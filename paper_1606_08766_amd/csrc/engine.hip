@@ -953,7 +953,9 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
   // bound is below cap)
   for (int c = 0; c < kNumClasses - 1; c++) {
     if (c > 0 && h_class_max[c - 1] >= cap) break;
-    const int rc = launch_class_sort<K, F32, PAY>(c, w, kin, pay_in, kout, perm_out, pay_out, w.cls_cap[c], st, t);
+    const int kinds = levels == 0 ? kInputOnly : (num_segs > 1 ? kMixed : 0);
+    const int rc = launch_class_sort<K, F32, PAY>(c | kinds, w, kin, pay_in, kout, perm_out, pay_out, w.cls_cap[c],
+                                                  st, t);
     if (rc) return rc;
   }
   {

@@ -98,6 +98,14 @@ __device__ __forceinline__ uint32_t get_bucket_id(const uint8_t* ids, uint64_t s
 // plain call as one segment in a single launch.  The kernels then receive a
 // negative class argument.
 constexpr int kDirect = 0x100;
+// Launcher flag: no sample-sort level ran, so every final segment lies in the
+// caller's input (positions implicit) and the class kernels need no table of
+// positions.
+constexpr int kInputOnly = 0x200;
+// Launcher flag: final segments of both kinds (a segmented call where some
+// user segments were split by levels): the class kernels run once for the
+// input segments and once for the buffer segments.
+constexpr int kMixed = 0x400;
 
 // Final segments of class cls (cls < 0: the direct single-segment mode).
 __device__ __forceinline__ uint32_t final_count(const Work& w, int cls) {

@@ -186,25 +186,26 @@ __device__ __forceinline__ Range4 block_range(K kmn, K kmx, uint32_t imn, uint32
 // ---------------------------------------------------------------------------
 // Bins of the word sort: a segment's words are distinct, so each word's rank
 // is the number of smaller words.  The words are first distributed into 2^LB
-// bins by the top bits of (word - smallest word), which keeps the bins in word
+// bins by the top bits of (word - lower bound), which keeps the bins in word
 // order; a word's rank is then the start of its bin plus the number of smaller
 // words inside the bin, found by comparing against the bin's words only.  On
 // the key distributions the sample sort leaves in a final segment (near
 // uniform over its range) a bin holds about 8 to 16 words, so this takes far
-// fewer steps than a merge sort's log2(len) rounds.  Skewed segments, where a
-// bin would hold more than kBinLimit words, are left to the merge sort.
-constexpr uint32_t kBinLimit = 128;
+// fewer steps than a merge sort's log2(len) rounds.  The ranking costs about
+// the sum over the bins of size^2 compares; where that exceeds kRankBudget per
+// word (runs of equal keys, keys clustered far apart) the segment is left to
+// the merge sort.
+constexpr uint32_t kRankBudget = 128;
 
 // Bin phase: c holds the element words, element j = i * THREADS + t as c[i];
 // elements j >= len are not used; every word lies in [wlo, whi].  Counts the
 // words of each bin (bin[0 .. S] are zero on entry; r receives each word's
 // place among its bin's words, in no particular order), turns the counts into
-// bin starts (bin[S] = len) and
-// returns, uniformly over the block, whether every bin holds at most
-// kBinLimit words.  shift receives the bin shift: a word's bin is
-// (word - wlo) >> shift.
+// bin starts (bin[S] = len) and returns, uniformly over the block, whether
+// the ranking fits kRankBudget.  shift receives the bin shift: a word's bin
+// is (word - wlo) >> shift.  tmp holds THREADS/64 + 1 64-bit values.
 template <int THREADS, int ITEMS, int LB>
-__device__ __forceinline__ bool bin_count(const uint64_t (&c)[ITEMS], uint32_t len, uint32_t* bin, uint32_t* tmp,
+__device__ __forceinline__ bool bin_count(const uint64_t (&c)[ITEMS], uint32_t len, uint32_t* bin, uint64_t* tmp,
                                           int t, uint64_t wlo, uint64_t whi, int& shift, uint32_t (&r)[ITEMS]) {
   constexpr int S = 1 << LB;
   constexpr int SPT = (S + THREADS - 1) / THREADS;  // bins scanned per thread
@@ -218,16 +219,18 @@ __device__ __forceinline__ bool bin_count(const uint64_t (&c)[ITEMS], uint32_t l
     if ((uint32_t)(i * THREADS + t) < len) r[i] = atomicAdd(&bin[(uint32_t)((c[i] - wmn) >> shift)], 1u);
   }
   __syncthreads();
-  uint32_t loc[SPT], sum = 0;
-  bool over = false;
+  // one scan of (sum of squared bin sizes, bin size): the low half gives the
+  // bin starts, the high half's total the ranking cost (both fit 32 bits)
+  uint32_t loc[SPT];
+  uint64_t v = 0;
 #pragma unroll
   for (int s = 0; s < SPT; s++) {
     const int b = t * SPT + s;
     loc[s] = b < S ? bin[b] : 0u;
-    over = over | (loc[s] > kBinLimit);
-    sum += loc[s];
+    v += ((uint64_t)(loc[s] * loc[s]) << 32) | loc[s];
   }
-  uint32_t e = block_excl_scan<THREADS>(sum, tmp, nullptr);
+  uint64_t total;
+  uint32_t e = (uint32_t)block_excl_scan<THREADS, uint64_t>(v, tmp, &total);
 #pragma unroll
   for (int s = 0; s < SPT; s++) {
     const int b = t * SPT + s;
@@ -235,7 +238,8 @@ __device__ __forceinline__ bool bin_count(const uint64_t (&c)[ITEMS], uint32_t l
     e += loc[s];
   }
   if (t == 0) bin[S] = len;
-  return !__syncthreads_or(over);
+  __syncthreads();
+  return (total >> 32) <= (uint64_t)kRankBudget * len;
 }
 
 // Rank phase, after bin_count succeeded: places the words in their bins (in
@@ -305,9 +309,13 @@ __device__ __forceinline__ void bin_rank(const uint64_t (&c)[ITEMS], const uint3
 // sort.  A segment whose check finds a pair out of order is marked kPairsFlag
 // and sorted by k_local_sort<FLAGGED> launched last.  Every path produces the
 // same output; words take half the LDS of pairs and one compare per step.
-template <typename K, bool F32, bool PAY, int THREADS, int ITEMS, bool MERGE = false>
+// SRCBUF false: the instance for segments of the caller's input only (no
+// table of positions); true: for buffer segments, and for input segments too
+// unless `mixed` (then the other instance takes those).
+template <typename K, bool F32, bool PAY, int THREADS, int ITEMS, bool MERGE = false, bool SRCBUF = true>
 __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const K* in_keys, const uint32_t* in_pay,
-                                                         K* keys_out, uint32_t* perm_out, uint32_t* pay_out) {
+                                                         K* keys_out, uint32_t* perm_out, uint32_t* pay_out,
+                                                         int mixed) {
   constexpr int N = THREADS * ITEMS;
   constexpr int NP = lpad_size(N);
   constexpr int PB = 32 - __builtin_clz((unsigned)(N - 1));
@@ -323,16 +331,18 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
   uint32_t* const s_hi = s_lo + NP;
   __shared__ uint32_t s_red[6 * (THREADS / kWave)];
   __shared__ uint32_t s_bin[BINS ? (1 << LB) + 1 : 1];
-  __shared__ uint32_t s_tmp[THREADS / kWave + 1];
+  __shared__ uint64_t s_tmp[THREADS / kWave + 1];
   // positions of the segment's elements by slot (for segments of a buffer),
-  // loaded coalesced with the keys
-  __shared__ uint32_t s_idx[N];
+  // loaded coalesced with the keys; SRCBUF false: every segment lies in the
+  // caller's input and positions are slots
+  __shared__ uint32_t s_idx[SRCBUF ? N : 1];
   static_assert(!BINS || NP >= N + 3, "room for the words read past a bin's end");
   const uint32_t cnt_c = final_count(w, cls);
   for (uint32_t q = blockIdx.x; q < cnt_c; q += gridDim.x) {
     FinalSeg f = final_at(w, cls, q);
     if (MERGE && !(f.src & kMergeFlag)) continue;  // uniform
     f.src &= 0xFFu;
+    if (SRCBUF ? (mixed && f.src == 0) : f.src != 0) continue;  // the other instance's
     // an opaque copy of the thread index: per-thread addresses are recomputed
     // per segment rather than hoisted out of the loop and kept live
     int tid = threadIdx.x;
@@ -340,7 +350,7 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
     const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
     const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
     const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
-    auto idx_at = [&](uint32_t j) -> uint32_t { return f.src ? s_idx[j] : j; };
+    auto idx_at = [&](uint32_t j) -> uint32_t { return (SRCBUF && f.src) ? s_idx[j] : j; };
     auto key_at = [&](uint32_t j) -> K { return f.src ? srck[f.start + j] : load_ord<K, F32>(srck, f.start + j); };
     // thread t takes slots i*THREADS+t (striped, coalesced); keys wait in the
     // word memory (not in registers) until the minimum is known
@@ -352,7 +362,7 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
       if (j < f.len) {
         K key;
         uint32_t idx = j;
-        if (f.src) {
+        if (SRCBUF && f.src) {
           key = srck[f.start + j];
           idx = srci[f.start + j];
           s_idx[j] = idx;
@@ -584,6 +594,8 @@ static int merge_class_launch(int c, const Work& w, const K* kin, const uint32_t
   static const std::string t_pairs = "(k_local_sort<K, F32, PAY, " + shape + ">)";
   static const std::string t_words = "(k_local_words<K, F32, PAY, " + shape + ">)";
   static const std::string t_merge = "(k_local_words<K, F32, PAY, " + shape + ", true>)";
+  static const std::string t_words_in = "(k_local_words<K, F32, PAY, " + shape + ", false, false>)";
+  static const std::string t_merge_in = "(k_local_words<K, F32, PAY, " + shape + ", true, false>)";
   static const std::string t_flagged = "(k_local_sort<K, F32, PAY, " + shape + ", true>)";
   if (c & kDirect) {
     RS_LAUNCH_TAGGED((k_local_sort<K, F32, PAY, T, I>), t_pairs.c_str(), 1, T, st, w, -1, kin, pay_in, kout,
@@ -592,12 +604,23 @@ static int merge_class_launch(int c, const Work& w, const K* kin, const uint32_t
   }
   // the word sort takes about one workgroup per segment (bounded); the pair
   // sort of the rare handed-over segments a resident-sized grid
-  RS_LAUNCH_TAGGED((k_local_words<K, F32, PAY, T, I>), t_words.c_str(), grid_for(cap_c, RS_WORDS_PER_CU), T, st, w,
-                   c, kin, pay_in, kout, perm_out, pay_out);
-  if (T * I >= 1024)  // the binned instance hands skewed segments to the merged one
-    RS_LAUNCH_TAGGED((k_local_words<K, F32, PAY, T, I, true>), t_merge.c_str(), grid_for(cap_c, per), T, st, w, c,
-                     kin, pay_in, kout, perm_out, pay_out);
-  RS_LAUNCH_TAGGED((k_local_sort<K, F32, PAY, T, I, true>), t_flagged.c_str(), grid_for(cap_c, per), T, st, w, c,
+  const int cb = c & 0xFF;
+  const int mixed = (c & kMixed) ? 1 : 0;
+  if (c & (kInputOnly | kMixed)) {  // input segments
+    RS_LAUNCH_TAGGED((k_local_words<K, F32, PAY, T, I, false, false>), t_words_in.c_str(),
+                     grid_for(cap_c, RS_WORDS_PER_CU), T, st, w, cb, kin, pay_in, kout, perm_out, pay_out, mixed);
+    if (T * I >= 1024)  // the binned instance hands skewed segments to the merged one
+      RS_LAUNCH_TAGGED((k_local_words<K, F32, PAY, T, I, true, false>), t_merge_in.c_str(), grid_for(cap_c, per), T,
+                       st, w, cb, kin, pay_in, kout, perm_out, pay_out, mixed);
+  }
+  if (!(c & kInputOnly)) {  // buffer segments (and input ones unless mixed)
+    RS_LAUNCH_TAGGED((k_local_words<K, F32, PAY, T, I>), t_words.c_str(), grid_for(cap_c, RS_WORDS_PER_CU), T, st, w,
+                     cb, kin, pay_in, kout, perm_out, pay_out, mixed);
+    if (T * I >= 1024)
+      RS_LAUNCH_TAGGED((k_local_words<K, F32, PAY, T, I, true>), t_merge.c_str(), grid_for(cap_c, per), T, st, w, cb,
+                       kin, pay_in, kout, perm_out, pay_out, mixed);
+  }
+  RS_LAUNCH_TAGGED((k_local_sort<K, F32, PAY, T, I, true>), t_flagged.c_str(), grid_for(cap_c, per), T, st, w, cb,
                    kin, pay_in, kout, perm_out, pay_out);
   return 0;
 }

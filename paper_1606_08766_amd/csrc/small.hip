@@ -133,7 +133,7 @@ int launch_rfis_class(int c, const Work& w, const K* kin, const uint32_t* pay_in
                       uint32_t* pay_out, uint64_t cap_c, hipStream_t st) {
   const uint64_t slots = (uint64_t)num_cu_cached() * 16;
   const bool dir = (c & kDirect) != 0;
-  const int ca = dir ? -1 : c;
+  const int ca = dir ? -1 : (c & 0xFF);
   const uint32_t g1 = dir ? 1u : (uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots);
   const uint32_t g2 = dir ? 1u : (uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots / 2);
   switch (c & 0xFF) {
@@ -420,7 +420,7 @@ int launch_rquick_class(int c, const Work& w, const K* kin, const uint32_t* pay_
   const uint64_t slots = (uint64_t)num_cu_cached() * 2;
   const uint64_t seed = tuning().seed;
   const bool dir = (c & kDirect) != 0;
-  const int ca = dir ? -1 : c;
+  const int ca = dir ? -1 : (c & 0xFF);
   const uint32_t g = dir ? 1u : (uint32_t)std::min<uint64_t>(std::max<uint64_t>(cap_c, 1), slots);
   switch (c & 0xFF) {
     case 3:
