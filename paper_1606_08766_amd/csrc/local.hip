@@ -203,12 +203,14 @@ constexpr uint32_t kRankBudget = 128;
 // place among its bin's words, in no particular order), turns the counts into
 // bin starts (bin[S] = len) and returns, uniformly over the block, whether
 // the ranking fits kRankBudget.  shift receives the bin shift: a word's bin
-// is (word - wlo) >> shift.  tmp holds THREADS/64 + 1 64-bit values.
+// is (word - wlo) >> shift.  The first wave scans the bins (S / 64 per lane)
+// and leaves the ranking cost in *cost.
 template <int THREADS, int ITEMS, int LB>
-__device__ __forceinline__ bool bin_count(const uint64_t (&c)[ITEMS], uint32_t len, uint32_t* bin, uint64_t* tmp,
+__device__ __forceinline__ bool bin_count(const uint64_t (&c)[ITEMS], uint32_t len, uint32_t* bin, uint32_t* cost,
                                           int t, uint64_t wlo, uint64_t whi, int& shift, uint32_t (&r)[ITEMS]) {
   constexpr int S = 1 << LB;
-  constexpr int SPT = (S + THREADS - 1) / THREADS;  // bins scanned per thread
+  constexpr int PL = S / kWave;  // bins per lane of the scanning wave
+  static_assert(PL >= 1, "at least one bin per lane");
   const uint64_t wmn = wlo;
   const uint64_t range = whi - wlo;
   const int bits = range ? 64 - __clzll((long long)range) : 0;
@@ -219,27 +221,30 @@ __device__ __forceinline__ bool bin_count(const uint64_t (&c)[ITEMS], uint32_t l
     if ((uint32_t)(i * THREADS + t) < len) r[i] = atomicAdd(&bin[(uint32_t)((c[i] - wmn) >> shift)], 1u);
   }
   __syncthreads();
-  // one scan of (sum of squared bin sizes, bin size): the low half gives the
-  // bin starts, the high half's total the ranking cost (both fit 32 bits)
-  uint32_t loc[SPT];
-  uint64_t v = 0;
-#pragma unroll
-  for (int s = 0; s < SPT; s++) {
-    const int b = t * SPT + s;
-    loc[s] = b < S ? bin[b] : 0u;
-    v += ((uint64_t)(loc[s] * loc[s]) << 32) | loc[s];
+  if (t < kWave) {
+    // one scan of (sum of squared bin sizes, bin size): the low half gives
+    // the bin starts, the high half's total the ranking cost (both fit 32 bits)
+    uint64_t v = 0;
+#pragma unroll 4
+    for (int k = 0; k < PL; k++) {
+      const uint32_t x = bin[t * PL + k];
+      v += ((uint64_t)(x * x) << 32) | x;
+    }
+    const uint64_t inc = wave_incl_scan<uint64_t>(v);
+    uint32_t e = (uint32_t)(inc - v);
+#pragma unroll 4
+    for (int k = 0; k < PL; k++) {  // the counts are read again: fewer registers
+      const uint32_t x = bin[t * PL + k];
+      bin[t * PL + k] = e;
+      e += x;
+    }
+    if (t == kWave - 1) {
+      bin[S] = len;
+      *cost = (uint32_t)(inc >> 32);
+    }
   }
-  uint64_t total;
-  uint32_t e = (uint32_t)block_excl_scan<THREADS, uint64_t>(v, tmp, &total);
-#pragma unroll
-  for (int s = 0; s < SPT; s++) {
-    const int b = t * SPT + s;
-    if (b < S) bin[b] = e;
-    e += loc[s];
-  }
-  if (t == 0) bin[S] = len;
   __syncthreads();
-  return (total >> 32) <= (uint64_t)kRankBudget * len;
+  return *cost <= kRankBudget * len;
 }
 
 // Rank phase, after bin_count succeeded: places the words in their bins (in
@@ -331,7 +336,7 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
   uint32_t* const s_hi = s_lo + NP;
   __shared__ uint32_t s_red[6 * (THREADS / kWave)];
   __shared__ uint32_t s_bin[BINS ? (1 << LB) + 1 : 1];
-  __shared__ uint64_t s_tmp[THREADS / kWave + 1];
+  __shared__ uint32_t s_cost;
   // positions of the segment's elements by slot (for segments of a buffer),
   // loaded coalesced with the keys; SRCBUF false: every segment lies in the
   // caller's input and positions are slots
@@ -414,7 +419,7 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
                                  : (((uint64_t)range >> drop) << PB) | (uint64_t)(f.len - 1);
       int wsh;
       uint32_t r[ITEMS];
-      if (!bin_count<THREADS, ITEMS, LB>(c, f.len, s_bin, s_tmp, tid, wmn, wmx, wsh, r)) {
+      if (!bin_count<THREADS, ITEMS, LB>(c, f.len, s_bin, &s_cost, tid, wmn, wmx, wsh, r)) {
         // uniform; every thread is past its reads of this segment's LDS
         if (tid == 0) w.cls[cls][q].src = f.src | kMergeFlag;
         continue;
