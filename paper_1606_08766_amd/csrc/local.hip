@@ -197,28 +197,38 @@ __device__ __forceinline__ Range4 block_range(K kmn, K kmx, uint32_t imn, uint32
 // the merge sort.
 constexpr uint32_t kRankBudget = 128;
 
+// Bin of a word: with d = word - lo, ((d >> a) << b) | ((d >> c) & m), a
+// non-decreasing function of the word below 2^LB.  One field (m = 0): the top
+// LB bits of d.  Two fields, for exact words whose key range has fewer than
+// LB bits: the key part, then the top bits of (position - minimum position),
+// so that buckets with few distinct keys (long runs of equal keys) still
+// spread over the bins.
+struct BinMap {
+  uint64_t lo;
+  uint32_t a, b, c, m;
+  __device__ __forceinline__ uint32_t operator()(uint64_t w) const {
+    const uint64_t d = w - lo;
+    return ((uint32_t)(d >> a) << b) | ((uint32_t)(d >> c) & m);
+  }
+};
+
 // Bin phase: c holds the element words, element j = i * THREADS + t as c[i];
-// elements j >= len are not used; every word lies in [wlo, whi].  Counts the
-// words of each bin (bin[0 .. S] are zero on entry; r receives each word's
-// place among its bin's words, in no particular order), turns the counts into
-// bin starts (bin[S] = len) and returns, uniformly over the block, whether
-// the ranking fits kRankBudget.  shift receives the bin shift: a word's bin
-// is (word - wlo) >> shift.  The first wave scans the bins (S / 64 per lane)
-// and leaves the ranking cost in *cost.
+// elements j >= len are not used.  Counts the words of each bin (bin[0 .. S]
+// are zero on entry; r receives each word's place among its bin's words, in
+// no particular order), turns the counts into bin starts (bin[S] = len) and
+// returns, uniformly over the block, whether the ranking fits kRankBudget.
+// The first wave scans the bins (S / 64 per lane) and leaves the ranking
+// cost in *cost.
 template <int THREADS, int ITEMS, int LB>
 __device__ __forceinline__ bool bin_count(const uint64_t (&c)[ITEMS], uint32_t len, uint32_t* bin, uint32_t* cost,
-                                          int t, uint64_t wlo, uint64_t whi, int& shift, uint32_t (&r)[ITEMS]) {
+                                          int t, const BinMap& bm, uint32_t (&r)[ITEMS]) {
   constexpr int S = 1 << LB;
   constexpr int PL = S / kWave;  // bins per lane of the scanning wave
   static_assert(PL >= 1, "at least one bin per lane");
-  const uint64_t wmn = wlo;
-  const uint64_t range = whi - wlo;
-  const int bits = range ? 64 - __clzll((long long)range) : 0;
-  shift = bits > LB ? bits - LB : 0;
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) {
     r[i] = 0;
-    if ((uint32_t)(i * THREADS + t) < len) r[i] = atomicAdd(&bin[(uint32_t)((c[i] - wmn) >> shift)], 1u);
+    if ((uint32_t)(i * THREADS + t) < len) r[i] = atomicAdd(&bin[bm(c[i])], 1u);
   }
   __syncthreads();
   if (t < kWave) {
@@ -256,10 +266,10 @@ __device__ __forceinline__ bool bin_count(const uint64_t (&c)[ITEMS], uint32_t l
 template <int THREADS, int ITEMS, int LB>
 __device__ __forceinline__ void bin_rank(const uint64_t (&c)[ITEMS], const uint32_t (&r)[ITEMS], uint32_t len,
                                          uint64_t* wb, uint32_t* lo, uint32_t* hi, const uint32_t* bin, int t,
-                                         uint64_t wmn, int shift) {
+                                         const BinMap& bm) {
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) {
-    if ((uint32_t)(i * THREADS + t) < len) wb[bin[(uint32_t)((c[i] - wmn) >> shift)] + r[i]] = c[i];
+    if ((uint32_t)(i * THREADS + t) < len) wb[bin[bm(c[i])] + r[i]] = c[i];
   }
   if (t < 3) wb[len + t] = ~0ull;
   __syncthreads();
@@ -271,7 +281,7 @@ __device__ __forceinline__ void bin_rank(const uint64_t (&c)[ITEMS], const uint3
   for (int i = 0; i < ITEMS; i++) {
     const uint32_t p = i * THREADS + t;  // < N: inside wb
     const uint64_t w = wb[p];
-    uint32_t db = (uint32_t)((w - wmn) >> shift);
+    uint32_t db = bm(w);
     db = p < len ? db : 0u;
     const uint32_t s0 = bin[db];
     const uint32_t s1 = p < len ? bin[db + 1] : s0;
@@ -414,17 +424,26 @@ __global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const 
       // bounds of the words: exact words are at least (position min) and at
       // most (key range, position max, all slot bits); slot words lie in
       // [0, (key range >> drop, len - 1)]
-      const uint64_t wmn = exact ? (uint64_t)imn << XB : 0ull;
-      const uint64_t wmx = exact ? ((uint64_t)range << sh) | ((uint64_t)imx << XB) | (PAY ? SLOT : 0ull)
-                                 : (((uint64_t)range >> drop) << PB) | (uint64_t)(f.len - 1);
-      int wsh;
+      BinMap bm;
+      if (exact && rb < LB) {  // key part, then the top bits of the position
+        const uint32_t ib = LB - rb, ir = imx - imn;
+        const int ibits = ir ? 32 - __clz(ir) : 0;
+        bm = BinMap{(uint64_t)imn << XB, (uint32_t)sh, ib, (uint32_t)(XB + max(ibits - (int)ib, 0)), (1u << ib) - 1u};
+      } else {
+        const uint64_t wmn = exact ? (uint64_t)imn << XB : 0ull;
+        const uint64_t wmx = exact ? ((uint64_t)range << sh) | ((uint64_t)imx << XB) | (PAY ? SLOT : 0ull)
+                                   : (((uint64_t)range >> drop) << PB) | (uint64_t)(f.len - 1);
+        const uint64_t wr = wmx - wmn;
+        const int bits = wr ? 64 - __clzll((long long)wr) : 0;
+        bm = BinMap{wmn, (uint32_t)(bits > LB ? bits - LB : 0), 0u, 0u, 0u};
+      }
       uint32_t r[ITEMS];
-      if (!bin_count<THREADS, ITEMS, LB>(c, f.len, s_bin, &s_cost, tid, wmn, wmx, wsh, r)) {
+      if (!bin_count<THREADS, ITEMS, LB>(c, f.len, s_bin, &s_cost, tid, bm, r)) {
         // uniform; every thread is past its reads of this segment's LDS
         if (tid == 0) w.cls[cls][q].src = f.src | kMergeFlag;
         continue;
       }
-      bin_rank<THREADS, ITEMS, LB>(c, r, f.len, s_words, s_lo, s_hi, s_bin, tid, wmn, wsh);
+      bin_rank<THREADS, ITEMS, LB>(c, r, f.len, s_words, s_lo, s_hi, s_bin, tid, bm);
     } else {
       __syncthreads();  // every key read from the word memory
       lds_merge_sort_words<THREADS, ITEMS>(c, s_lo, s_hi, tid);
