@@ -60,29 +60,34 @@ __device__ __forceinline__ uint32_t logk_for(uint32_t len, uint32_t target, uint
 
 __device__ __forceinline__ void set_status(Ctl* ctl, int32_t code) { atomicCAS(&ctl->status, 0, code); }
 
-// Append one segment per active lane either to the list of segments the
-// next level splits (to_big) or to the final list of its size class.  Wave
-// aggregated; every lane of the wave must call it.
-__device__ __forceinline__ void route(const Work& w, uint32_t* big_counter, BigSeg* big_list, bool active,
-                                      bool to_big, uint64_t start, uint64_t ubase, uint32_t len, uint32_t src,
-                                      uint32_t cap, uint32_t ff, uint32_t target, uint32_t left) {
-  const bool ab = active && to_big, af = active && !to_big;
-  const uint32_t i = wave_append(big_counter, 0u, ab);
-  if (ab) {
-    if (i < w.big_max)
-      big_list[i] = BigSeg{start, ubase, len, logk_for(len, target, left)};
-    else
-      set_status(w.ctl, -3);  // capacity bound violated: internal error
+// Routing of a block's segments to the list of segments to split (index
+// kNumClasses) or to the final lists by size class, aggregated per block:
+// slots are counted in LDS (one LDS atomic per list and wave), then one
+// global atomic per list and block reserves them.  Every thread of the block
+// calls once per iteration of a block-uniform loop; `lds` is zeroed before
+// the first call (route_lds_init) and is left zeroed.
+struct RouteLds {
+  uint32_t cnt[kNumClasses + 1];
+  uint32_t base[kNumClasses + 1];
+  unsigned long long keys[kNumClasses];
+};
+
+__device__ __forceinline__ void route_lds_init(RouteLds& L) {
+  if (threadIdx.x <= (unsigned)kNumClasses) {
+    L.cnt[threadIdx.x] = 0;
+    if (threadIdx.x < (unsigned)kNumClasses) L.keys[threadIdx.x] = 0;
   }
-  const uint32_t c = af ? class_of(len, cap, ff) : 0u;
-  const uint32_t j = wave_append(w.ctl->class_count, c, af);
-  if (af) {
-    if (j < w.cls_cap[c])
-      w.cls[c][j] = FinalSeg{start, len, src};
-    else
-      set_status(w.ctl, -3);
-  }
-  // keys per class (statistics): one 64-bit atomic per distinct class per wave
+  __syncthreads();
+}
+
+__device__ __forceinline__ void route(const Work& w, RouteLds& L, uint32_t* big_counter, BigSeg* big_list,
+                                      bool active, bool to_big, uint64_t start, uint64_t ubase, uint32_t len,
+                                      uint32_t src, uint32_t cap, uint32_t ff, uint32_t target, uint32_t left) {
+  const uint32_t c = (active && !to_big) ? class_of(len, cap, ff) : 0u;
+  const uint32_t dest = to_big ? (uint32_t)kNumClasses : c;
+  const uint32_t li = wave_append(L.cnt, dest, active);
+  // keys per class (statistics): one LDS atomic per distinct class per wave
+  const bool af = active && !to_big;
   uint64_t pending = __ballot(af);
   while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
@@ -90,8 +95,32 @@ __device__ __forceinline__ void route(const Work& w, uint32_t* big_counter, BigS
     const bool mine = af && c == k;
     uint64_t sum = mine ? (uint64_t)len : 0ull;
     for (int d = kWave / 2; d > 0; d >>= 1) sum += __shfl_xor(sum, d, kWave);
-    if (lane_id() == (uint32_t)leader) atomicAdd((unsigned long long*)&w.ctl->class_keys[k], (unsigned long long)sum);
+    if (lane_id() == (uint32_t)leader) atomicAdd(&L.keys[k], (unsigned long long)sum);
     pending &= ~__ballot(mine);
+  }
+  __syncthreads();
+  if (threadIdx.x <= (unsigned)kNumClasses) {
+    const uint32_t t = threadIdx.x, n = L.cnt[t];
+    uint32_t* ctr = t == (uint32_t)kNumClasses ? big_counter : &w.ctl->class_count[t];
+    L.base[t] = n ? atomicAdd(ctr, n) : 0u;
+    if (t < (uint32_t)kNumClasses && L.keys[t]) atomicAdd((unsigned long long*)&w.ctl->class_keys[t], L.keys[t]);
+    L.cnt[t] = 0;
+    if (t < (uint32_t)kNumClasses) L.keys[t] = 0;
+  }
+  __syncthreads();
+  if (active) {
+    const uint32_t i = L.base[dest] + li;
+    if (to_big) {
+      if (i < w.big_max)
+        big_list[i] = BigSeg{start, ubase, len, logk_for(len, target, left)};
+      else
+        set_status(w.ctl, -3);  // capacity bound violated: internal error
+    } else {
+      if (i < w.cls_cap[c])
+        w.cls[c][i] = FinalSeg{start, len, src};
+      else
+        set_status(w.ctl, -3);
+    }
   }
 }
 
@@ -105,6 +134,8 @@ __global__ void k_reset(Ctl* ctl, uint32_t levels) {
 // Route every user segment: split it (big list 0) or sort it directly.
 __global__ void k_init(Work w, const uint64_t* seg_off, uint32_t num_segs, uint64_t n_total, uint32_t cap,
                        uint32_t target, uint32_t levels, uint32_t ff) {
+  __shared__ RouteLds L;
+  route_lds_init(L);
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t s0 = blockIdx.x * blockDim.x; s0 < num_segs; s0 += stride) {
     const uint32_t s = s0 + threadIdx.x;
@@ -121,7 +152,7 @@ __global__ void k_init(Work w, const uint64_t* seg_off, uint32_t num_segs, uint6
     }
     const uint32_t len = active ? (uint32_t)(b - a) : 0u;
     active = active && len > 0;
-    route(w, &w.ctl->big_count[0], w.big[0], active, len > cap && levels > 0, a, a, len, 0u, cap, ff, target,
+    route(w, L, &w.ctl->big_count[0], w.big[0], active, len > cap && levels > 0, a, a, len, 0u, cap, ff, target,
           levels);
   }
 }
@@ -689,6 +720,8 @@ __global__ void k_level_end(Work w, int lev, uint32_t cap, uint32_t target, int 
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
   const uint64_t total = (uint64_t)m * kMaxK;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  __shared__ RouteLds L;
+  route_lds_init(L);
   for (uint64_t g0 = (uint64_t)blockIdx.x * blockDim.x; g0 < total; g0 += stride) {
     const uint64_t g = g0 + threadIdx.x;
     bool active = g < total;
@@ -722,8 +755,8 @@ __global__ void k_level_end(Work w, int lev, uint32_t cap, uint32_t target, int 
       }
     }
     active = active && len > 0;
-    route(w, &w.ctl->big_count[cur ^ 1], w.big[cur ^ 1], active, len > cap && !last, bs.start + lo, bs.ubase, len,
-          dst_code, cap, ff, target, left);
+    route(w, L, &w.ctl->big_count[cur ^ 1], w.big[cur ^ 1], active, len > cap && !last, bs.start + lo, bs.ubase,
+          len, dst_code, cap, ff, target, left);
   }
 }
 
@@ -904,7 +937,8 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
     return launch_class_sort<K, F32, PAY>(c | kDirect, w, kin, pay_in, kout, perm_out, pay_out, 1, st, t);
   }
   RS_LAUNCH(k_reset, 1, 256, st, w.ctl, levels);
-  RS_LAUNCH(k_init, grid_for((num_segs + 255) / 256, 4), 256, st, w, seg_off, num_segs, n, cap, target, levels, ff);
+  RS_LAUNCH(k_init, grid_for((num_segs + 1023) / 1024, 1), 1024, st, w, seg_off, num_segs, n, cap, target, levels,
+            ff);
 
   const uint32_t tile_log2 = t.tile_log2 == 12 ? 12 : 13;
   const uint64_t groups_max = (n >> w.group_log2) + w.big_max + 1;
