@@ -14,7 +14,7 @@ struct Tuning {
   uint32_t target = 6144;     // bucket size a level aims for (at most cap / 2)
   uint32_t cap = 12288;       // largest bucket sorted in LDS
   uint32_t max_levels = 4;
-  uint32_t rfis_max = 256;    // classes with upper bound <= rfis_max use RFIS
+  uint32_t rfis_max = 64;     // classes with upper bound <= rfis_max use RFIS
   uint32_t rquick_max = 1;    // classes with upper bound <= rquick_max use RQuick
   uint64_t seed = 0x5EED5EED12345678ull;
   uint32_t tile_log2 = 13;  // scatter tile: 2^tile_log2 keys
