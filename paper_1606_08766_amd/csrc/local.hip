@@ -328,7 +328,7 @@ __device__ __forceinline__ void bin_rank(const uint64_t (&c)[ITEMS], const uint3
 // table of positions); true: for buffer segments, and for input segments too
 // unless `mixed` (then the other instance takes those).
 template <typename K, bool F32, bool PAY, int THREADS, int ITEMS, bool MERGE = false, bool SRCBUF = true>
-__global__ __launch_bounds__(THREADS) void k_local_words(Work w, int cls, const K* in_keys, const uint32_t* in_pay,
+__global__ __launch_bounds__(THREADS, (THREADS >= 1024 ? 8 : 1)) void k_local_words(Work w, int cls, const K* in_keys, const uint32_t* in_pay,
                                                          K* keys_out, uint32_t* perm_out, uint32_t* pay_out,
                                                          int mixed) {
   constexpr int N = THREADS * ITEMS;
