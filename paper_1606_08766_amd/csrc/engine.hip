@@ -993,6 +993,10 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
     if (rc) return rc;
   }
   {
+    const int rc = launch_local_fallbacks<K, F32, PAY>(w, cap, kin, pay_in, kout, perm_out, pay_out, st);
+    if (rc) return rc;
+  }
+  {
     const int rc = launch_oversize<K, F32, PAY>(w, kin, pay_in, kout, perm_out, pay_out, w.cls_cap[kNumClasses - 1], st);
     if (rc) return rc;
   }

@@ -42,6 +42,12 @@ template <typename K, bool F32, bool PAY>
 int launch_rquick_class(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
                         uint32_t* pay_out, uint64_t cap_c, hipStream_t st);
 
+// Segments the word sorts handed over (merge sort of words, then pair sort),
+// launched once after all classes (local.hip).
+template <typename K, bool F32, bool PAY>
+int launch_local_fallbacks(const Work& w, uint32_t cap, const K* kin, const uint32_t* pay_in, K* kout,
+                           uint32_t* perm_out, uint32_t* pay_out, hipStream_t st);
+
 // Global-memory fallback sort of final segments longer than cap (local.hip).
 template <typename K, bool F32, bool PAY>
 int launch_oversize(const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,

@@ -25,9 +25,39 @@ struct Shape {
 
 
 // ---------------------------------------------------------------------------
+// The final segments a class kernel sorts.  flag 0: segment q = blockIdx.x +
+// i * gridDim.x of class cls.  Otherwise (the launches after all classes):
+// every segment of every class whose src carries `flag`; each thread checks
+// one segment and the flagged ones are collected in LDS (s_list holds THREADS
+// entries), so that the search is parallel rather than a chain of dependent
+// loads.  body(cc, q) runs on every thread of the block.
+template <int THREADS, typename F>
+__device__ __forceinline__ void for_each_segment(const Work& w, int cls, uint32_t flag, uint32_t* s_list,
+                                                 uint32_t& s_n, F&& body) {
+  if (!flag) {
+    const uint32_t cnt = final_count(w, cls);
+    for (uint32_t q = blockIdx.x; q < cnt; q += gridDim.x) body(cls, q);
+    return;
+  }
+  for (int cc = 0; cc <= kNumClasses - 2; cc++) {
+    const uint32_t cnt = final_count(w, cc);
+    for (uint32_t q0 = blockIdx.x * THREADS; q0 < cnt; q0 += gridDim.x * THREADS) {
+      if (threadIdx.x == 0) s_n = 0;
+      __syncthreads();
+      const uint32_t q = q0 + threadIdx.x;
+      if (q < cnt && (w.cls[cc][q].src & flag)) s_list[atomicAdd(&s_n, 1u)] = q;
+      __syncthreads();
+      const uint32_t n = s_n;
+      for (uint32_t k = 0; k < n; k++) body(cc, s_list[k]);
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Final segments of one size class: one workgroup each, sorted in LDS as
-// (key, position) pairs.  FLAGGED: only the segments the word sort below
-// handed over (kPairsFlag).
+// (key, position) pairs.  FLAGGED: the segments of every class that the word
+// sort below handed over (kPairsFlag); the shape then fits the largest class.
 template <typename K, bool F32, bool PAY, int THREADS, int ITEMS, bool FLAGGED = false>
 __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K* in_keys, const uint32_t* in_pay,
                                                         K* keys_out, uint32_t* perm_out, uint32_t* pay_out) {
@@ -39,10 +69,11 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
   __shared__ uint32_t s_p[PAY ? NP : 1];
   const LdsArr<K> sa{s_lo, s_hi, s_v, s_p};
   direct_reset(w, cls);
-  const uint32_t cnt_c = final_count(w, cls);
-  for (uint32_t q = blockIdx.x; q < cnt_c; q += gridDim.x) {
-    FinalSeg f = final_at(w, cls, q);
-    if (FLAGGED && !(f.src & kPairsFlag)) continue;  // uniform
+  __shared__ uint32_t s_list[FLAGGED ? THREADS : 1];
+  __shared__ uint32_t s_n;
+  for_each_segment<THREADS>(w, cls, FLAGGED ? kPairsFlag : 0u, s_list, s_n, [&](int cc, uint32_t q) {
+    FinalSeg f = final_at(w, cc, q);
+    if (FLAGGED && !(f.src & kPairsFlag)) return;  // uniform
     f.src &= 0xFFu;
     const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
     const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
@@ -83,7 +114,7 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
       if constexpr (PAY) pay_out[f.start + j] = srcp[f.start + s_p[q]];
     }
     __syncthreads();
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -318,11 +349,12 @@ __device__ __forceinline__ void bin_rank(const uint64_t (&c)[ITEMS], const uint3
 //                 only in dropped low bits) come out in slot order, which is
 //                 checked against their (key, position) order afterwards.
 // The words are distinct.  Segments of at least 1024 elements are ordered by
-// bins and ranks (bin_count, bin_rank); a segment where a bin is too full is
-// marked kMergeFlag and left to the MERGE instance launched next, which (like
-// the instances for shorter segments) sorts the words with the LDS merge
-// sort.  A segment whose check finds a pair out of order is marked kPairsFlag
-// and sorted by k_local_sort<FLAGGED> launched last.  Every path produces the
+// bins and ranks (bin_count, bin_rank); a segment whose ranking would cost too
+// much is marked kMergeFlag and left to the MERGE instance, launched once
+// after all classes with the largest class's shape, which (like the
+// instances for shorter segments) sorts the words with the LDS merge sort.  A
+// segment whose check finds a pair out of order is marked kPairsFlag and
+// sorted by k_local_sort<FLAGGED>, launched last.  Every path produces the
 // same output; words take half the LDS of pairs and one compare per step.
 // SRCBUF false: the instance for segments of the caller's input only (no
 // table of positions); true: for buffer segments, and for input segments too
@@ -352,12 +384,13 @@ __global__ __launch_bounds__(THREADS, (THREADS >= 1024 ? 8 : 1)) void k_local_wo
   // caller's input and positions are slots
   __shared__ uint32_t s_idx[SRCBUF ? N : 1];
   static_assert(!BINS || NP >= N + 3, "room for the words read past a bin's end");
-  const uint32_t cnt_c = final_count(w, cls);
-  for (uint32_t q = blockIdx.x; q < cnt_c; q += gridDim.x) {
-    FinalSeg f = final_at(w, cls, q);
-    if (MERGE && !(f.src & kMergeFlag)) continue;  // uniform
+  __shared__ uint32_t s_list[MERGE ? THREADS : 1];
+  __shared__ uint32_t s_n;
+  for_each_segment<THREADS>(w, cls, MERGE ? kMergeFlag : 0u, s_list, s_n, [&](int cc, uint32_t q) {
+    FinalSeg f = final_at(w, cc, q);
+    if (MERGE && !(f.src & kMergeFlag)) return;  // uniform
     f.src &= 0xFFu;
-    if (SRCBUF ? (mixed && f.src == 0) : f.src != 0) continue;  // the other instance's
+    if (SRCBUF ? (mixed && f.src == 0) : f.src != 0) return;  // the other instance's
     // an opaque copy of the thread index: per-thread addresses are recomputed
     // per segment rather than hoisted out of the loop and kept live
     int tid = threadIdx.x;
@@ -440,8 +473,8 @@ __global__ __launch_bounds__(THREADS, (THREADS >= 1024 ? 8 : 1)) void k_local_wo
       uint32_t r[ITEMS];
       if (!bin_count<THREADS, ITEMS, LB>(c, f.len, s_bin, &s_cost, tid, bm, r)) {
         // uniform; every thread is past its reads of this segment's LDS
-        if (tid == 0) w.cls[cls][q].src = f.src | kMergeFlag;
-        continue;
+        if (tid == 0) w.cls[cc][q].src = f.src | kMergeFlag;
+        return;
       }
       bin_rank<THREADS, ITEMS, LB>(c, r, f.len, s_words, s_lo, s_hi, s_bin, tid, bm);
     } else {
@@ -482,8 +515,8 @@ __global__ __launch_bounds__(THREADS, (THREADS >= 1024 ? 8 : 1)) void k_local_wo
       if (perm_out) perm_out[f.start + j] = idx;
       if constexpr (PAY) pay_out[f.start + j] = srcp[f.start + slot];
     }
-    if (__syncthreads_or(bad) && threadIdx.x == 0) w.cls[cls][q].src = f.src | kPairsFlag;
-  }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) w.cls[cc][q].src = f.src | kPairsFlag;
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -612,50 +645,63 @@ __global__ __launch_bounds__(THREADS) void k_oversize(Work w, const K* in_keys, 
 #endif
 template <typename K, bool F32, bool PAY, int T, int I>
 static int merge_class_launch(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout,
-                              uint32_t* perm_out, uint32_t* pay_out, uint64_t cap_c, uint32_t per,
-                              hipStream_t st) {
+                              uint32_t* perm_out, uint32_t* pay_out, uint64_t cap_c, hipStream_t st) {
   static const std::string shape = std::to_string(T) + ", " + std::to_string(I);
   static const std::string t_pairs = "(k_local_sort<K, F32, PAY, " + shape + ">)";
   static const std::string t_words = "(k_local_words<K, F32, PAY, " + shape + ">)";
-  static const std::string t_merge = "(k_local_words<K, F32, PAY, " + shape + ", true>)";
   static const std::string t_words_in = "(k_local_words<K, F32, PAY, " + shape + ", false, false>)";
-  static const std::string t_merge_in = "(k_local_words<K, F32, PAY, " + shape + ", true, false>)";
-  static const std::string t_flagged = "(k_local_sort<K, F32, PAY, " + shape + ", true>)";
   if (c & kDirect) {
     RS_LAUNCH_TAGGED((k_local_sort<K, F32, PAY, T, I>), t_pairs.c_str(), 1, T, st, w, -1, kin, pay_in, kout,
                      perm_out, pay_out);
     return 0;
   }
-  // the word sort takes about one workgroup per segment (bounded); the pair
-  // sort of the rare handed-over segments a resident-sized grid
+  // the word sort takes about one workgroup per segment (bounded); handed-over
+  // segments are sorted by launch_local_fallbacks after all classes
   const int cb = c & 0xFF;
   const int mixed = (c & kMixed) ? 1 : 0;
-  if (c & (kInputOnly | kMixed)) {  // input segments
+  if (c & (kInputOnly | kMixed))  // input segments
     RS_LAUNCH_TAGGED((k_local_words<K, F32, PAY, T, I, false, false>), t_words_in.c_str(),
                      grid_for(cap_c, RS_WORDS_PER_CU), T, st, w, cb, kin, pay_in, kout, perm_out, pay_out, mixed);
-    if (T * I >= 1024)  // the binned instance hands skewed segments to the merged one
-      RS_LAUNCH_TAGGED((k_local_words<K, F32, PAY, T, I, true, false>), t_merge_in.c_str(), grid_for(cap_c, per), T,
-                       st, w, cb, kin, pay_in, kout, perm_out, pay_out, mixed);
-  }
-  if (!(c & kInputOnly)) {  // buffer segments (and input ones unless mixed)
+  if (!(c & kInputOnly))  // buffer segments (and input ones unless mixed)
     RS_LAUNCH_TAGGED((k_local_words<K, F32, PAY, T, I>), t_words.c_str(), grid_for(cap_c, RS_WORDS_PER_CU), T, st, w,
                      cb, kin, pay_in, kout, perm_out, pay_out, mixed);
-    if (T * I >= 1024)
-      RS_LAUNCH_TAGGED((k_local_words<K, F32, PAY, T, I, true>), t_merge.c_str(), grid_for(cap_c, per), T, st, w, cb,
-                       kin, pay_in, kout, perm_out, pay_out, mixed);
-  }
-  RS_LAUNCH_TAGGED((k_local_sort<K, F32, PAY, T, I, true>), t_flagged.c_str(), grid_for(cap_c, per), T, st, w, cb,
-                   kin, pay_in, kout, perm_out, pay_out);
   return 0;
+}
+
+// The segments the word sorts of all classes handed over: the merge sort of
+// words for those whose ranking was too costly, then the pair sort for those
+// whose word order failed the check.  One resident-sized launch each, with
+// the shape of the largest class a call can have.
+template <typename K, bool F32, bool PAY, int T, int I>
+static int fallback_launch(const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
+                            uint32_t* pay_out, hipStream_t st) {
+  static const std::string shape = std::to_string(T) + ", " + std::to_string(I);
+  static const std::string t_merge = "(k_local_words<K, F32, PAY, " + shape + ", true>)";
+  static const std::string t_flagged = "(k_local_sort<K, F32, PAY, " + shape + ", true>)";
+  const uint32_t g = grid_for(1u << 30, 1);
+  RS_LAUNCH_TAGGED((k_local_words<K, F32, PAY, T, I, true>), t_merge.c_str(), g, T, st, w, 0, kin, pay_in, kout,
+                   perm_out, pay_out, 0);
+  RS_LAUNCH_TAGGED((k_local_sort<K, F32, PAY, T, I, true>), t_flagged.c_str(), g, T, st, w, 0, kin, pay_in, kout,
+                   perm_out, pay_out);
+  return 0;
+}
+
+template <typename K, bool F32, bool PAY>
+int launch_local_fallbacks(const Work& w, uint32_t cap, const K* kin, const uint32_t* pay_in, K* kout,
+                           uint32_t* perm_out, uint32_t* pay_out, hipStream_t st) {
+  if constexpr (!PAY) {
+    if (cap > 8192) return fallback_launch<K, F32, PAY, 768, 16>(w, kin, pay_in, kout, perm_out, pay_out, st);
+  }
+  return fallback_launch<K, F32, PAY, 1024, 8>(w, kin, pay_in, kout, perm_out, pay_out, st);
 }
 
 template <typename K, bool F32, bool PAY>
 int launch_merge_class(int c, const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
                        uint32_t* pay_out, uint64_t cap_c, hipStream_t st) {
   const int cb = c & 0xFF;
-  auto go = [&](auto tag, uint32_t per) -> int {
+  auto go = [&](auto tag, uint32_t) -> int {
     constexpr int T = decltype(tag)::T, I = decltype(tag)::I;
-    return merge_class_launch<K, F32, PAY, T, I>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, per, st);
+    return merge_class_launch<K, F32, PAY, T, I>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, st);
   };
   switch (cb) {
     case 0: return go(Shape<64, 1>{}, 16);
@@ -677,7 +723,9 @@ int launch_merge_class(int c, const Work& w, const K* kin, const uint32_t* pay_i
 
 #define RS_INST_MERGE(K, F, P)                                                                                 \
   template int launch_merge_class<K, F, P>(int, const Work&, const K*, const uint32_t*, K*, uint32_t*, uint32_t*, \
-                                           uint64_t, hipStream_t);
+                                           uint64_t, hipStream_t);                                              \
+  template int launch_local_fallbacks<K, F, P>(const Work&, uint32_t, const K*, const uint32_t*, K*, uint32_t*,   \
+                                               uint32_t*, hipStream_t);
 RS_INST_MERGE(uint32_t, false, false)
 RS_INST_MERGE(uint32_t, true, false)
 RS_INST_MERGE(uint64_t, false, false)
