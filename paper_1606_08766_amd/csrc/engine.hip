@@ -198,13 +198,22 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev) {
 // The k-1 splitters are stored as an implicit binary search tree: node t at
 // depth d, index q = t - 2^d within its depth, holds splitter number
 // (2q+1) * 2^(logk-1-d) (1-based, in sorted order).
+constexpr uint32_t kSplRankBudget = 64;  // compares per sample the ranking path may take
+
 template <typename K, bool F32, bool SRC_IN, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K* in_keys, int src_buf,
                                                        uint32_t a, uint64_t seed) {
-  constexpr int NP = lpad_size(THREADS * ITEMS);
+  constexpr int N = THREADS * ITEMS;
+  constexpr int NP = lpad_size(N);
+  constexpr int LB = 31 - __builtin_clz((unsigned)(N / 8));  // bins of the ranking path
+  constexpr int PL = (1 << LB) / kWave;
+  static_assert(PL >= 1, "one bin per lane at least");
   __shared__ uint32_t s_lo[NP];
   __shared__ uint32_t s_hi[sizeof(K) == 8 ? NP : 1];
   __shared__ uint32_t s_v[NP];
+  __shared__ uint32_t s_bin[(1 << LB) + 1];
+  __shared__ uint32_t s_red[6 * (THREADS / kWave)];
+  __shared__ uint32_t s_cost;
   const LdsArr<K> sa{s_lo, s_hi, s_v, nullptr};
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
@@ -237,26 +246,128 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
       }
       p[i] = 0;
     }
-    lds_merge_sort<K, THREADS, ITEMS, false>(k, v, p, sa);
-#pragma unroll
-    for (int i = 0; i < ITEMS; i++) sa.put(lpad(threadIdx.x * ITEMS + i), k[i], v[i]);
-    __syncthreads();
     const uint32_t kk = 1u << bs.logk;
-    for (uint32_t node = threadIdx.x + 1; node < kk; node += THREADS) {
-      const uint32_t d = 31u - __clz(node);
-      const uint32_t q = node - (1u << d);
-      const uint32_t j = (2u * q + 1u) << (bs.logk - 1u - d);
-      const uint32_t r = j * ae - 1u;
-      tkey[(uint64_t)s * kMaxK + node] = sa.key(lpad(r));
-      w.tree_idx[(uint64_t)s * kMaxK + node] = s_v[lpad(r)];
-    }
-    if (lev == 0 && s == 0) {
-      for (uint32_t j = threadIdx.x + 1; j < kk; j += THREADS) {
-        w.ctl->l0_spl_key[j - 1] = (uint64_t)sa.key(lpad(j * ae - 1u));
-        w.ctl->l0_spl_pos[j - 1] = s_v[lpad(j * ae - 1u)];
+    // The splitters are the samples of rank j * ae - 1 (j = 1 .. kk - 1) in
+    // (key, position) order.  Ranks come from bins, as in the word sort:
+    // samples are counted into bins by the top bits of (key - min) (or, for a
+    // narrow key range, key offset then position bits), and a sample's rank
+    // is its bin's start plus the number of smaller samples in its bin.  If
+    // that would cost more than kRankBudget compares per sample, the samples
+    // are merge sorted instead.
+    bool ranked = false;
+    {
+      K kmn = KMax<K>::v, kmx = K(0);
+      uint32_t imn = ~0u, imx = 0u;
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        if (threadIdx.x * ITEMS + i < S) {
+          kmn = k[i] < kmn ? k[i] : kmn;
+          kmx = k[i] > kmx ? k[i] : kmx;
+          imn = min(imn, v[i]);
+          imx = max(imx, v[i]);
+        }
       }
-      if (threadIdx.x == 0) w.ctl->l0_k = kk;
+      for (int b = threadIdx.x; b <= (1 << LB); b += THREADS) s_bin[b] = 0;
+      const Range4 br = block_range<K, THREADS>(kmn, kmx, imn, imx, s_red, threadIdx.x);
+      kmn = (K)br.kmn;
+      const uint64_t kr = (uint64_t)((K)br.kmx - kmn);
+      const int rb = kr ? 64 - __clzll((long long)kr) : 0;
+      BinMap bm;
+      const bool narrow = rb < LB;  // bins: key offset, then the top bits of the position
+      if (narrow) {
+        const uint32_t ib = LB - rb, ir = br.imx - br.imn;
+        const int ibits = ir ? 32 - __clz(ir) : 0;
+        bm = BinMap{(uint64_t)br.imn, 32u, ib, (uint32_t)max(ibits - (int)ib, 0), (1u << ib) - 1u};
+      } else {
+        bm = BinMap{0ull, (uint32_t)(rb - LB), 0u, 0u, 0u};
+      }
+      auto bin_of = [&](K key, uint32_t idx) -> uint32_t {
+        const uint64_t off = (uint64_t)(K)(key - kmn);
+        return bm(narrow ? (off << 32) | idx : off);
+      };
+      uint32_t r[ITEMS];
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        r[i] = 0;
+        if (threadIdx.x * ITEMS + i < S) r[i] = atomicAdd(&s_bin[bin_of(k[i], v[i])], 1u);
+      }
+      __syncthreads();
+      if (threadIdx.x < kWave) {  // one wave scans the bins and sums their squared sizes
+        uint64_t acc = 0;
+        for (int q = 0; q < PL; q++) {
+          const uint32_t x = s_bin[threadIdx.x * PL + q];
+          acc += ((uint64_t)(x * x) << 32) | x;
+        }
+        const uint64_t inc = wave_incl_scan<uint64_t>(acc);
+        uint32_t e = (uint32_t)(inc - acc);
+        for (int q = 0; q < PL; q++) {
+          const uint32_t x = s_bin[threadIdx.x * PL + q];
+          s_bin[threadIdx.x * PL + q] = e;
+          e += x;
+        }
+        if (threadIdx.x == kWave - 1) {
+          s_bin[1 << LB] = S;
+          s_cost = (uint32_t)(inc >> 32);
+        }
+      }
+      __syncthreads();
+      if (s_cost <= kSplRankBudget * S) {  // uniform
+        ranked = true;
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+          if (threadIdx.x * ITEMS + i < S) sa.put(s_bin[bin_of(k[i], v[i])] + r[i], k[i], v[i]);
+        }
+        __syncthreads();
+        for (uint32_t pq = threadIdx.x; pq < S; pq += THREADS) {
+          const K key = sa.key(pq);
+          const uint32_t idx = s_v[pq];
+          const uint32_t db = bin_of(key, idx);
+          const uint32_t s0 = s_bin[db], s1 = s_bin[db + 1];
+          // samples are drawn with replacement: equal samples are ranked by
+          // their place in the bin, so that every rank is taken once
+          uint32_t less = 0;
+          for (uint32_t q = s0; q < s1; q++) {
+            const K kq = sa.key(q);
+            const uint32_t iq = s_v[q];
+            less += (pair_less(kq, iq, key, idx) || (kq == key && iq == idx && q < pq)) ? 1u : 0u;
+          }
+          const uint32_t rank = s0 + less;
+          if ((rank + 1) % ae == 0) {
+            const uint32_t j = (rank + 1) / ae;
+            if (j < kk) {
+              const uint32_t node = (j | kk) >> (__builtin_ctz(j) + 1);
+              tkey[(uint64_t)s * kMaxK + node] = key;
+              w.tree_idx[(uint64_t)s * kMaxK + node] = idx;
+              if (lev == 0 && s == 0) {
+                w.ctl->l0_spl_key[j - 1] = (uint64_t)key;
+                w.ctl->l0_spl_pos[j - 1] = idx;
+              }
+            }
+          }
+        }
+      }
     }
+    if (!ranked) {
+      lds_merge_sort<K, THREADS, ITEMS, false>(k, v, p, sa);
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) sa.put(lpad(threadIdx.x * ITEMS + i), k[i], v[i]);
+      __syncthreads();
+      for (uint32_t node = threadIdx.x + 1; node < kk; node += THREADS) {
+        const uint32_t d = 31u - __clz(node);
+        const uint32_t q = node - (1u << d);
+        const uint32_t j = (2u * q + 1u) << (bs.logk - 1u - d);
+        const uint32_t r = j * ae - 1u;
+        tkey[(uint64_t)s * kMaxK + node] = sa.key(lpad(r));
+        w.tree_idx[(uint64_t)s * kMaxK + node] = s_v[lpad(r)];
+      }
+      if (lev == 0 && s == 0) {
+        for (uint32_t j = threadIdx.x + 1; j < kk; j += THREADS) {
+          w.ctl->l0_spl_key[j - 1] = (uint64_t)sa.key(lpad(j * ae - 1u));
+          w.ctl->l0_spl_pos[j - 1] = s_v[lpad(j * ae - 1u)];
+        }
+      }
+    }
+    if (lev == 0 && s == 0 && threadIdx.x == 0) w.ctl->l0_k = kk;
     __syncthreads();
   }
 }

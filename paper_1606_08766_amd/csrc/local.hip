@@ -118,103 +118,6 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
 }
 
 // ---------------------------------------------------------------------------
-// Block-wide minimum and maximum of the keys and of the positions (every
-// thread of the block calls, every lane active).  Lanes of a row of 16 are
-// combined with DPP moves (xor 1, xor 2, then the half-row and row mirrors),
-// the four rows of a wave by lane reads into scalar registers, the waves
-// through LDS (one row of lanes reads the per-wave values).  The results are
-// uniform and live in scalar registers.  red holds 6 * THREADS/64 words.
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
-}
-template <int CTRL>
-__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
-  return ((uint64_t)dpp_u32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp_u32<CTRL>((uint32_t)v);
-}
-__device__ __forceinline__ uint32_t lane_u32(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
-__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int l) {
-  return ((uint64_t)lane_u32((uint32_t)(v >> 32), l) << 32) | lane_u32((uint32_t)v, l);
-}
-struct Range4 {  // key minimum and maximum (as 64 bits), position minimum and maximum
-  uint64_t kmn, kmx;
-  uint32_t imn, imx;
-};
-
-template <typename K>
-__device__ __forceinline__ void row_reduce(K& kmn, K& kmx, uint32_t& imn, uint32_t& imx) {
-  auto step = [&](auto ctrl) {
-    constexpr int C = decltype(ctrl)::value;
-    K a, b;
-    if constexpr (sizeof(K) == 8) {
-      a = (K)dpp_u64<C>((uint64_t)kmn);
-      b = (K)dpp_u64<C>((uint64_t)kmx);
-    } else {
-      a = (K)dpp_u32<C>((uint32_t)kmn);
-      b = (K)dpp_u32<C>((uint32_t)kmx);
-    }
-    const uint32_t c = dpp_u32<C>(imn), d = dpp_u32<C>(imx);
-    kmn = a < kmn ? a : kmn;
-    kmx = b > kmx ? b : kmx;
-    imn = min(imn, c);
-    imx = max(imx, d);
-  };
-  step(std::integral_constant<int, 0xB1>{});   // quad_perm [1,0,3,2]
-  step(std::integral_constant<int, 0x4E>{});   // quad_perm [2,3,0,1]
-  step(std::integral_constant<int, 0x141>{});  // row_half_mirror
-  step(std::integral_constant<int, 0x140>{});  // row_mirror
-}
-
-template <typename K>
-__device__ __forceinline__ Range4 rows_to_scalar(K kmn, K kmx, uint32_t imn, uint32_t imx, int rows) {
-  Range4 r{~0ull, 0ull, ~0u, 0u};
-  for (int q = 0; q < rows; q++) {
-    uint64_t a, b;
-    if constexpr (sizeof(K) == 8) {
-      a = lane_u64((uint64_t)kmn, 16 * q);
-      b = lane_u64((uint64_t)kmx, 16 * q);
-    } else {
-      a = lane_u32((uint32_t)kmn, 16 * q);
-      b = lane_u32((uint32_t)kmx, 16 * q);
-    }
-    const uint32_t c = lane_u32(imn, 16 * q), d = lane_u32(imx, 16 * q);
-    r.kmn = a < r.kmn ? a : r.kmn;
-    r.kmx = b > r.kmx ? b : r.kmx;
-    r.imn = min(r.imn, c);
-    r.imx = max(r.imx, d);
-  }
-  return r;
-}
-
-template <typename K, int THREADS>
-__device__ __forceinline__ Range4 block_range(K kmn, K kmx, uint32_t imn, uint32_t imx, uint32_t* red, int t) {
-  constexpr int NW = THREADS / kWave;
-  static_assert(NW <= 16, "per-wave values fit one row");
-  row_reduce<K>(kmn, kmx, imn, imx);
-  const Range4 wv = rows_to_scalar<K>(kmn, kmx, imn, imx, 4);
-  const int w = t / kWave, lane = t % kWave;
-  if (lane == 0) {
-    red[6 * w + 0] = (uint32_t)wv.kmn;
-    red[6 * w + 1] = (uint32_t)(wv.kmn >> 32);
-    red[6 * w + 2] = (uint32_t)wv.kmx;
-    red[6 * w + 3] = (uint32_t)(wv.kmx >> 32);
-    red[6 * w + 4] = wv.imn;
-    red[6 * w + 5] = wv.imx;
-  }
-  __syncthreads();
-  K a = KMax<K>::v, b = K(0);
-  uint32_t c = ~0u, d = 0u;
-  if (lane < NW) {
-    a = (K)(((uint64_t)red[6 * lane + 1] << 32) | red[6 * lane + 0]);
-    b = (K)(((uint64_t)red[6 * lane + 3] << 32) | red[6 * lane + 2]);
-    c = red[6 * lane + 4];
-    d = red[6 * lane + 5];
-  }
-  row_reduce<K>(a, b, c, d);
-  return rows_to_scalar<K>(a, b, c, d, 1);
-}
-
-// ---------------------------------------------------------------------------
 // Bins of the word sort: a segment's words are distinct, so each word's rank
 // is the number of smaller words.  The words are first distributed into 2^LB
 // bins by the top bits of (word - lower bound), which keeps the bins in word
@@ -227,21 +130,6 @@ __device__ __forceinline__ Range4 block_range(K kmn, K kmx, uint32_t imn, uint32
 // word (runs of equal keys, keys clustered far apart) the segment is left to
 // the merge sort.
 constexpr uint32_t kRankBudget = 128;
-
-// Bin of a word: with d = word - lo, ((d >> a) << b) | ((d >> c) & m), a
-// non-decreasing function of the word below 2^LB.  One field (m = 0): the top
-// LB bits of d.  Two fields, for exact words whose key range has fewer than
-// LB bits: the key part, then the top bits of (position - minimum position),
-// so that buckets with few distinct keys (long runs of equal keys) still
-// spread over the bins.
-struct BinMap {
-  uint64_t lo;
-  uint32_t a, b, c, m;
-  __device__ __forceinline__ uint32_t operator()(uint64_t w) const {
-    const uint64_t d = w - lo;
-    return ((uint32_t)(d >> a) << b) | ((uint32_t)(d >> c) & m);
-  }
-};
 
 // Bin phase: c holds the element words, element j = i * THREADS + t as c[i];
 // elements j >= len are not used.  Counts the words of each bin (bin[0 .. S]
