@@ -152,7 +152,6 @@ def bench_plain(args, R, torch):
     torch.cuda.synchronize()
     # per-distribution time (events around each step; reported, not the metric)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    R.timing_begin()
     t0 = time.perf_counter()
     for s in range(args.steps):
         ev[s][0].record()
@@ -160,6 +159,12 @@ def bench_plain(args, R, torch):
         ev[s][1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # the same steps again with an event pair around every kernel launch, for
+    # the per-pass figures (kept out of the timed region above)
+    R.timing_begin()
+    for s in range(args.steps):
+        R.sort(inputs[s % len(DISTS)], workspace=ws, out=(ko, po))
+    torch.cuda.synchronize()
     timing = R.timing_end()
     per_dist = {}
     for s in range(args.steps):
@@ -276,8 +281,12 @@ def bench_batched(args, R, torch):
     del keys, pay
     ko, po, plo = torch.empty_like(dk), torch.empty(n, dtype=torch.uint32, device="cuda"), torch.empty_like(dp)
     ws = torch.empty(R.segmented_workspace_bytes(R.U64, n, count, True), dtype=torch.uint8, device="cuda")
-    R.timing_begin()
     t_b = _timed(torch, lambda: R.segmented_sort(dk, do, dp, workspace=ws, out=(ko, po, plo)), args.steps, args.warmup)
+    # per-pass figures from a separate, instrumented run
+    R.timing_begin()
+    for _ in range(args.steps):
+        R.segmented_sort(dk, do, dp, workspace=ws, out=(ko, po, plo))
+    torch.cuda.synchronize()
     timing = R.timing_end()
     if R.workspace_status(ws) != 0:
         raise RuntimeError("segmented sort reported an error")
@@ -298,7 +307,7 @@ def bench_batched(args, R, torch):
     batched = n / t_b / 1e9
     plain = npl / t_p / 1e9
     per = {}
-    calls = args.steps + args.warmup  # the event log spans the warmup calls too
+    calls = args.steps
     for name, (cnt, ms) in timing.items():
         c = kernel_class(name)
         per[c] = round(per.get(c, 0.0) + ms / calls, 4)
