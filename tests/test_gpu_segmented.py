@@ -100,3 +100,26 @@ def test_forced_fallback_path(kt):
     keys, pay, off = gen.segmented(kt, sizes, ["uniform", "zero", "deterdupl", "uniform", "uniform"], seed=8)
     with R.tuned(force_fallback=1):
         check_against_oracle(keys, off, pay)
+
+
+@pytest.mark.parametrize("kt", ["u64", "u32"])
+@pytest.mark.parametrize("with_payload", [False, True])
+def test_clustered_segments_take_the_merge_path(kt, with_payload):
+    """Segments whose keys form two clusters far apart: the bins by the top
+    key bits put about half of each segment into one bin, so the ranking cost
+    exceeds its budget and the merge instance after the classes sorts them.
+    Mixed with a segment large enough for sample-sort levels, so that both
+    the input-segment and the buffer-segment instances run."""
+    rng = np.random.default_rng(21)
+    dt = np.uint64 if kt == "u64" else np.uint32
+    hi = dt(1) << dt(60 if kt == "u64" else 28)
+    sizes = [1500, 3000, 5000, 8000, 100000, 2500]
+    parts = []
+    for n in sizes:
+        a = rng.integers(0, 1000, n).astype(dt)
+        a[rng.random(n) < 0.5] += hi
+        parts.append(a)
+    keys = np.concatenate(parts)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    pay = rng.integers(0, 1 << 32, keys.size, dtype=np.uint64).astype(np.uint32) if with_payload else None
+    check_against_oracle(keys, off, pay)
