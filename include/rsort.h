@@ -135,11 +135,11 @@ int rsort_class_stats(const void *workspace, void *stream, uint32_t max_classes,
  * after it returns (process-wide, not thread-safe against concurrent calls).
  * ---------------------------------------------------------------------- */
 typedef struct {
-  uint32_t oversample;   /* samples per bucket a (sample size a * k) */
-  uint32_t target;       /* bucket size a level aims for */
+  uint32_t oversample;   /* samples per bucket a (sample size a * k; default 32) */
+  uint32_t target;       /* bucket size a level aims for (default 6144, at most cap / 2) */
   uint32_t cap;          /* largest bucket sorted in LDS; larger ones are split */
   uint32_t max_levels;   /* upper bound on sample-sort levels */
-  uint32_t rfis_max;     /* segments <= rfis_max use RFIS (0 disables: set 1) */
+  uint32_t rfis_max;     /* segments <= rfis_max use RFIS (default 64; 0 keeps, 1 disables) */
   uint32_t rquick_max;   /* segments <= rquick_max (and > rfis_max) use RQuick */
   uint64_t seed;         /* seed of the sample positions and coin flips */
   uint32_t tile_log2;    /* log2 of keys per scatter tile (12 or 13; counting uses 12) */
