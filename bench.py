@@ -91,14 +91,15 @@ def kernel_class(name: str) -> str:
 
 def pass_bytes_per_key(ks: int):
     """Algorithmic HBM bytes per key of each pass (read + write) for keys of
-    ks bytes, u32 positions and levels of at most 256 buckets (one-byte
-    bucket ids between the second level's count and scatter)."""
+    ks bytes, u32 positions, (key, position) records in the level buffers and
+    levels of at most 256 buckets (one-byte bucket ids between the second
+    level's count and scatter)."""
     return {
         "count_l1": ks,                 # read keys
-        "scatter_l1": ks + ks + 4,      # read keys; write key + position
-        "count_l2": ks + 1,             # read keys (positions only for keys tying a splitter key); write bucket id
-        "scatter_l2": 2 * (ks + 4) + 1,  # read key + position + bucket id; write key + position
-        "local_sort": 2 * (ks + 4),     # read key + position; write key + perm
+        "scatter_l1": ks + ks + 4,      # read keys; write (key, position) records
+        "count_l2": ks + 4 + 1,         # read records; write bucket id
+        "scatter_l2": 2 * (ks + 4) + 1,  # read records + bucket id; write records
+        "local_sort": 2 * (ks + 4),     # read records; write key + perm
     }
 
 

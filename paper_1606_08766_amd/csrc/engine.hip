@@ -217,8 +217,7 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
   const LdsArr<K> sa{s_lo, s_hi, s_v, nullptr};
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
-  const K* bkey = SRC_IN ? nullptr : (const K*)w.buf_key[src_buf];
-  const uint32_t* bidx = SRC_IN ? nullptr : w.buf_idx[src_buf];
+  const BufView<K> bv{SRC_IN ? nullptr : w.buf_rec[src_buf]};
   K* tkey = (K*)w.tree_key;
   for (uint32_t s = blockIdx.x; s < m; s += gridDim.x) {
     const BigSeg bs = w.big[cur][s];
@@ -237,8 +236,7 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
           k[i] = load_ord<K, F32>(in_keys, pos);
           v[i] = (uint32_t)(pos - bs.ubase);
         } else {
-          k[i] = bkey[pos];
-          v[i] = bidx[pos];
+          bv.get(pos, k[i], v[i]);
         }
       } else {
         k[i] = KMax<K>::v;
@@ -522,8 +520,7 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
   const uint32_t G = w.ctl->total_groups;
-  const K* bkey = SRC_IN ? nullptr : (const K*)w.buf_key[src_buf];
-  const uint32_t* bidx = SRC_IN ? nullptr : w.buf_idx[src_buf];
+  const BufView<K> bv{SRC_IN ? nullptr : w.buf_rec[src_buf]};
   const uint32_t lane = lane_id();
   if (threadIdx.x == 0) {
     sc.gb = 1;
@@ -553,7 +550,7 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
           if constexpr (SRC_IN)
             key[i] = load_ord<K, F32>(in_keys, base + jj);
           else
-            key[i] = bkey[base + jj];
+            key[i] = bv.key(base + jj);
         }
       }
       uint32_t b[ITEMS];
@@ -564,7 +561,7 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
                                  if constexpr (SRC_IN)
                                    return (uint32_t)(pos - ub);
                                  else
-                                   return bidx[pos];
+                                   return bv.idx(pos);
                                },
                                b);
       if constexpr (!SRC_IN) {
@@ -681,11 +678,9 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
   const uint32_t G = w.ctl->total_groups;
-  const K* bkey = SRC_IN ? nullptr : (const K*)w.buf_key[src_buf];
-  const uint32_t* bidx = SRC_IN ? nullptr : w.buf_idx[src_buf];
+  const BufView<K> bv{SRC_IN ? nullptr : w.buf_rec[src_buf]};
   const uint32_t* bpay = SRC_IN ? in_pay : w.buf_pay[src_buf];
-  K* dkey = (K*)w.buf_key[dst_buf];
-  uint32_t* didx = w.buf_idx[dst_buf];
+  const BufView<K> dv{w.buf_rec[dst_buf]};
   uint32_t* dpay = w.buf_pay[dst_buf];
   const uint32_t lane = lane_id();
   if (threadIdx.x == 0) {
@@ -727,8 +722,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
             nkey[i] = load_ord<K, F32>(in_keys, base + jj);
             nidx[i] = (uint32_t)(base + jj - bs.ubase);
           } else {
-            nkey[i] = bkey[base + jj];
-            nidx[i] = bidx[base + jj];
+            bv.get(base + jj, nkey[i], nidx[i]);
             nb[i] = get_bucket_id(w.ids, bs.start, (uint64_t)tl * TILE + jj, bs.logk);
           }
           if constexpr (PAY) npay[i] = bpay[base + jj];
@@ -808,8 +802,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
       }
       for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) {
         const uint64_t g = gdelta[stage_b[p]] + p;
-        dkey[g] = stage[p];
-        didx[g] = stage32[p];
+        dv.put(g, stage[p], stage32[p]);
       }
       if constexpr (PAY) {
         __syncthreads();
@@ -950,10 +943,9 @@ size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, 
   }
   const uint64_t nb = (levels || t.force_fallback) ? n : 0;
   const uint64_t o_ids = take(levels >= 2 ? 2 * n : 0);
-  uint64_t o_bk[2], o_bi[2], o_bp[2];
+  uint64_t o_bk[2], o_bp[2];
   for (int b = 0; b < 2; b++) {
-    o_bk[b] = take(nb * ks);
-    o_bi[b] = take(nb * 4);
+    o_bk[b] = take(nb * (ks + 4));
     o_bp[b] = take(pay ? nb * 4 : 0);
   }
   if (w) {
@@ -972,8 +964,7 @@ size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, 
       w->cls_cap[c] = cls_cap[c];
     }
     for (int b = 0; b < 2; b++) {
-      w->buf_key[b] = base + o_bk[b];
-      w->buf_idx[b] = (uint32_t*)(base + o_bi[b]);
+      w->buf_rec[b] = (uint32_t*)(base + o_bk[b]);
       w->buf_pay[b] = pay ? (uint32_t*)(base + o_bp[b]) : nullptr;
     }
     w->ids = levels >= 2 ? (uint8_t*)(base + o_ids) : nullptr;

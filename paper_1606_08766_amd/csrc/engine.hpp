@@ -71,8 +71,7 @@ struct Work {
   uint32_t* partials;    // [scan_blocks + 1]
   FinalSeg* cls[kNumClasses];     // per size class lists
   uint64_t cls_cap[kNumClasses];
-  void* buf_key[2];      // A, B: [n] keys (ordinal)
-  uint32_t* buf_idx[2];  // [n]
+  uint32_t* buf_rec[2];  // A, B: [n] element records (ordinal key, position; see BufView)
   uint32_t* buf_pay[2];  // [n] (payload calls only)
   uint8_t* ids;          // [2 n] bucket of each element of a buffer level (see bucket ids below)
   uint64_t big_max, count_max, scan_blocks, n;
@@ -92,6 +91,47 @@ __device__ __forceinline__ void put_bucket_id(uint8_t* ids, uint64_t s, uint64_t
 }
 __device__ __forceinline__ uint32_t get_bucket_id(const uint8_t* ids, uint64_t s, uint64_t r, uint32_t logk) {
   return logk <= 8 ? (uint32_t)ids[2 * s + r] : (uint32_t)((const uint16_t*)(ids + 2 * s))[r];
+}
+
+// The element buffers of the levels interleave each element's ordinal key
+// and input position in one record of 32-bit words (key low, key high for
+// 64-bit keys, then the position), so that one memory instruction moves a
+// whole element; a scatter writes half as many partial lines as with
+// separate key and position arrays.
+template <typename K>
+struct BufView {
+  static constexpr int W = (int)(sizeof(K) / 4) + 1;  // words per record
+  uint32_t* p;
+  __device__ __forceinline__ K key(uint64_t i) const {
+    const uint32_t* r = p + i * W;
+    if constexpr (sizeof(K) == 8)
+      return ((uint64_t)r[1] << 32) | r[0];
+    else
+      return r[0];
+  }
+  __device__ __forceinline__ uint32_t idx(uint64_t i) const { return p[i * W + W - 1]; }
+  __device__ __forceinline__ void get(uint64_t i, K& k, uint32_t& v) const {
+    const uint32_t* r = p + i * W;
+    if constexpr (sizeof(K) == 8) {
+      const uint32_t a = r[0], b = r[1], c = r[2];
+      k = ((uint64_t)b << 32) | a;
+      v = c;
+    } else {
+      const uint32_t a = r[0], c = r[1];
+      k = a;
+      v = c;
+    }
+  }
+  __device__ __forceinline__ void put(uint64_t i, K k, uint32_t v) const {
+    uint32_t* r = p + i * W;
+    r[0] = (uint32_t)k;
+    if constexpr (sizeof(K) == 8) r[1] = (uint32_t)((uint64_t)k >> 32);
+    r[W - 1] = v;
+  }
+};
+template <typename K>
+__device__ __forceinline__ BufView<K> buf_view(const Work& w, int b) {
+  return BufView<K>{w.buf_rec[b]};
 }
 
 // Launcher flag (or-ed into the class index): sort the whole input of a

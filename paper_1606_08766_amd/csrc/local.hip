@@ -75,8 +75,7 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
     FinalSeg f = final_at(w, cc, q);
     if (FLAGGED && !(f.src & kPairsFlag)) return;  // uniform
     f.src &= 0xFFu;
-    const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
-    const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
+    const BufView<K> sb{f.src ? w.buf_rec[f.src - 1] : nullptr};
     const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
     K k[ITEMS];
     uint32_t v[ITEMS], p[ITEMS];
@@ -87,10 +86,9 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
       const uint32_t j = i * THREADS + threadIdx.x;
       if (j < f.len) {
         if (f.src) {
-          k[i] = srck[f.start + j];
-          v[i] = srci[f.start + j];
+          sb.get(f.start + j, k[i], v[i]);
         } else {
-          k[i] = load_ord<K, F32>(srck, f.start + j);
+          k[i] = load_ord<K, F32>(in_keys, f.start + j);
           v[i] = j;
         }
       } else {
@@ -283,11 +281,10 @@ __global__ __launch_bounds__(THREADS, (THREADS >= 1024 ? 8 : 1)) void k_local_wo
     // per segment rather than hoisted out of the loop and kept live
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
-    const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
+    const BufView<K> sb{f.src ? w.buf_rec[f.src - 1] : nullptr};
     const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
     auto idx_at = [&](uint32_t j) -> uint32_t { return (SRCBUF && f.src) ? s_idx[j] : j; };
-    auto key_at = [&](uint32_t j) -> K { return f.src ? srck[f.start + j] : load_ord<K, F32>(srck, f.start + j); };
+    auto key_at = [&](uint32_t j) -> K { return f.src ? sb.key(f.start + j) : load_ord<K, F32>(in_keys, f.start + j); };
     // thread t takes slots i*THREADS+t (striped, coalesced); keys wait in the
     // word memory (not in registers) until the minimum is known
     K mn = KMax<K>::v, mx = K(0);
@@ -299,11 +296,10 @@ __global__ __launch_bounds__(THREADS, (THREADS >= 1024 ? 8 : 1)) void k_local_wo
         K key;
         uint32_t idx = j;
         if (SRCBUF && f.src) {
-          key = srck[f.start + j];
-          idx = srci[f.start + j];
+          sb.get(f.start + j, key, idx);
           s_idx[j] = idx;
         } else {
-          key = load_ord<K, F32>(srck, f.start + j);
+          key = load_ord<K, F32>(in_keys, f.start + j);
         }
         s_words[j] = (uint64_t)key;
         mn = key < mn ? key : mn;
@@ -434,8 +430,7 @@ __global__ __launch_bounds__(THREADS) void k_oversize(Work w, const K* in_keys, 
     // buffers used: data source code f.src; first target is the other buffer
     // pass 0 writes into the buffer that does not hold the data
     int cur = f.src == 0 ? 0 : ((int)f.src - 1) ^ 1;
-    const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
-    const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
+    const BufView<K> sb{f.src ? w.buf_rec[f.src - 1] : nullptr};
     const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
     // pass 0: sort chunks of C in LDS
     for (uint32_t c0 = 0; c0 < f.len; c0 += C) {
@@ -445,8 +440,12 @@ __global__ __launch_bounds__(THREADS) void k_oversize(Work w, const K* in_keys, 
       for (int i = 0; i < ITEMS; i++) {
         const uint32_t j = c0 + threadIdx.x * ITEMS + i;
         if (j < f.len) {
-          k[i] = f.src ? srck[f.start + j] : load_ord<K, F32>(srck, f.start + j);
-          v[i] = f.src ? srci[f.start + j] : j;
+          if (f.src) {
+            sb.get(f.start + j, k[i], v[i]);
+          } else {
+            k[i] = load_ord<K, F32>(in_keys, f.start + j);
+            v[i] = j;
+          }
           p[i] = PAY ? srcp[f.start + j] : 0u;
         } else {
           k[i] = KMax<K>::v;
@@ -455,15 +454,13 @@ __global__ __launch_bounds__(THREADS) void k_oversize(Work w, const K* in_keys, 
         }
       }
       block_merge_sort<K, THREADS, ITEMS, PAY>(k, v, p, sk, sv, sp);
-      K* dk = (K*)w.buf_key[cur];
-      uint32_t* dv = w.buf_idx[cur];
+      const BufView<K> db{w.buf_rec[cur]};
       uint32_t* dp = w.buf_pay[cur];
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         const uint32_t j = c0 + threadIdx.x * ITEMS + i;
         if (j < f.len) {
-          dk[f.start + j] = k[i];
-          dv[f.start + j] = v[i];
+          db.put(f.start + j, k[i], v[i]);
           if constexpr (PAY) dp[f.start + j] = p[i];
         }
       }
@@ -471,11 +468,9 @@ __global__ __launch_bounds__(THREADS) void k_oversize(Work w, const K* in_keys, 
     }
     // merge passes
     for (uint32_t run = C; run < f.len; run <<= 1) {
-      const K* ak = (const K*)w.buf_key[cur] + f.start;
-      const uint32_t* av = w.buf_idx[cur] + f.start;
+      const BufView<K> ab{w.buf_rec[cur] + f.start * BufView<K>::W};
       const uint32_t* ap = PAY ? w.buf_pay[cur] + f.start : nullptr;
-      K* dk = (K*)w.buf_key[cur ^ 1] + f.start;
-      uint32_t* dv = w.buf_idx[cur ^ 1] + f.start;
+      const BufView<K> db{w.buf_rec[cur ^ 1] + f.start * BufView<K>::W};
       uint32_t* dp = PAY ? w.buf_pay[cur ^ 1] + f.start : nullptr;
       for (uint32_t o0 = 0; o0 < f.len; o0 += THREADS) {
         const uint32_t o = o0 + threadIdx.x;  // output position handled by this thread
@@ -490,7 +485,7 @@ __global__ __launch_bounds__(THREADS) void k_oversize(Work w, const K* in_keys, 
           while (lo < hi) {
             const uint32_t mid = (lo + hi) >> 1;
             const uint32_t bj = b0 + d - 1 - mid;
-            if (pair_less(ak[bj], av[bj], ak[first + mid], av[first + mid]))
+            if (pair_less(ab.key(bj), ab.idx(bj), ab.key(first + mid), ab.idx(first + mid)))
               hi = mid;
             else
               lo = mid + 1;
@@ -502,10 +497,9 @@ __global__ __launch_bounds__(THREADS) void k_oversize(Work w, const K* in_keys, 
           else if (bi >= blen)
             takeA = true;
           else
-            takeA = !pair_less(ak[b0 + bi], av[b0 + bi], ak[first + ai], av[first + ai]);
+            takeA = !pair_less(ab.key(b0 + bi), ab.idx(b0 + bi), ab.key(first + ai), ab.idx(first + ai));
           const uint32_t sidx = takeA ? first + ai : b0 + bi;
-          dk[o] = ak[sidx];
-          dv[o] = av[sidx];
+          db.put(o, ab.key(sidx), ab.idx(sidx));
           if constexpr (PAY) dp[o] = ap[sidx];
         }
       }
@@ -513,12 +507,11 @@ __global__ __launch_bounds__(THREADS) void k_oversize(Work w, const K* in_keys, 
       cur ^= 1;
     }
     // output
-    const K* rk = (const K*)w.buf_key[cur] + f.start;
-    const uint32_t* rv = w.buf_idx[cur] + f.start;
+    const BufView<K> rb{w.buf_rec[cur] + f.start * BufView<K>::W};
     const uint32_t* rp = PAY ? w.buf_pay[cur] + f.start : nullptr;
     for (uint32_t j = threadIdx.x; j < f.len; j += THREADS) {
-      keys_out[f.start + j] = to_output<K, F32>(rk[j]);
-      if (perm_out) perm_out[f.start + j] = rv[j];
+      keys_out[f.start + j] = to_output<K, F32>(rb.key(j));
+      if (perm_out) perm_out[f.start + j] = rb.idx(j);
       if constexpr (PAY) pay_out[f.start + j] = rp[j];
     }
     __syncthreads();

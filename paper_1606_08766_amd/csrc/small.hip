@@ -66,16 +66,15 @@ __global__ __launch_bounds__(THREADS) void k_rfis(Work w, int cls, const K* in_k
   const uint32_t cnt = final_count(w, cls);
   for (uint32_t q = blockIdx.x; q < cnt; q += gridDim.x) {
     const FinalSeg f = final_at(w, cls, q);
-    const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
-    const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
+    const BufView<K> sb{f.src ? w.buf_rec[f.src - 1] : nullptr};
     const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
     T mine[PER];
 #pragma unroll
     for (int r = 0; r < PER; r++) {
       const uint32_t j = r * THREADS + threadIdx.x;
       if (j < f.len) {
-        const K key = f.src ? srck[f.start + j] : load_ord<K, F32>(srck, f.start + j);
-        const uint32_t idx = f.src ? srci[f.start + j] : j;
+        const K key = f.src ? sb.key(f.start + j) : load_ord<K, F32>(in_keys, f.start + j);
+        const uint32_t idx = f.src ? sb.idx(f.start + j) : j;
         mine[r] = RK::make(key, idx);
         sx[j] = mine[r];
       }
@@ -230,15 +229,14 @@ __global__ __launch_bounds__(THREADS) void k_rquick(Work w, int cls, const K* in
   const uint32_t cnt = final_count(w, cls);
   for (uint32_t q = blockIdx.x; q < cnt; q += gridDim.x) {
     const FinalSeg f = final_at(w, cls, q);
-    const K* srck = f.src ? (const K*)w.buf_key[f.src - 1] : in_keys;
-    const uint32_t* srci = f.src ? w.buf_idx[f.src - 1] : nullptr;
+    const BufView<K> sb{f.src ? w.buf_rec[f.src - 1] : nullptr};
     const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
     const uint32_t n = f.len;
     const uint64_t rstream = f.start * 0x9E3779B97F4A7C15ull + 0x52515549434Bull;
     // stage the input in buffer 1 (coalesced)
     for (uint32_t j = threadIdx.x; j < n; j += THREADS) {
-      bk[1][j] = f.src ? srck[f.start + j] : load_ord<K, F32>(srck, f.start + j);
-      bv[1][j] = f.src ? srci[f.start + j] : j;
+      bk[1][j] = f.src ? sb.key(f.start + j) : load_ord<K, F32>(in_keys, f.start + j);
+      bv[1][j] = f.src ? sb.idx(f.start + j) : j;
     }
     if (threadIdx.x < P) {
       off[threadIdx.x] = (uint32_t)((uint64_t)threadIdx.x * n / P);
