@@ -590,6 +590,43 @@ def trace_summary(stats_csv, command, out_path, title):
     print("\n".join(lines))
 
 
+def counter_table(csv_paths, command, out_path, title):
+    """Per-kernel means of any rocprofv3 --pmc counters (one or more
+    counter_collection.csv files, e.g. one per pass) as a short text table."""
+    import csv
+    from collections import defaultdict
+
+    agg = defaultdict(lambda: defaultdict(float))
+    disp = defaultdict(lambda: defaultdict(set))
+    for path in csv_paths:
+        for r in csv.DictReader(open(path)):
+            k = kernel_key(r["Kernel_Name"])
+            agg[k][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp[k][r["Counter_Name"]].add(r["Dispatch_Id"])
+    names = sorted({c for v in agg.values() for c in v})
+    lines = [title, "command: " + command, "source hash: " + src_hash(),
+             "values: mean per dispatch", "",
+             "%-28s " % "kernel" + " ".join("%16s" % c[:16] for c in names)]
+    order = sorted(agg, key=lambda k: -max(agg[k].values()))
+    for k in order[:16]:
+        vals = []
+        for c in names:
+            n = len(disp[k][c])
+            vals.append("%16.4g" % (agg[k][c] / n) if n else "%16s" % "-")
+        lines.append("%-28s " % k[:28] + " ".join(vals))
+    ratios = [("LDS bank-conflict cycles / LDS active cycles", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE"),
+              ("wave cycles waiting on anything / wave cycles", "SQ_WAIT_ANY", "SQ_WAVE_CYCLES")]
+    for label, a, b in ratios:
+        if a in names and b in names:
+            lines += ["", label]
+            for k in order[:16]:
+                if agg[k][b] > 0:
+                    lines.append("  %-28s %6.3f" % (k[:28], agg[k][a] / agg[k][b]))
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -598,6 +635,8 @@ def main():
                     help="summarise two rocprofv3 --pmc runs into profiles/ (no GPU needed)")
     ap.add_argument("--trace-summary", metavar="KERNEL_STATS_CSV",
                     help="summarise a rocprofv3 --stats run into profiles/ (no GPU needed)")
+    ap.add_argument("--counter-table", nargs="+", metavar="COUNTER_CSV",
+                    help="summarise rocprofv3 --pmc runs (any counters) into profiles/ (no GPU needed)")
     ap.add_argument("--profile-command", default="", help="command recorded in the summaries")
     ap.add_argument("--profile-name", default="kernel_trace_plain_2p28_u64.txt")
     ap.add_argument("--gpus", type=int, default=1)
@@ -613,6 +652,10 @@ def main():
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.calib_copy_mib or 1024, args.profile_command,
                     os.path.join(ROOT, "profiles"))
+        return
+    if args.counter_table:
+        counter_table(args.counter_table, args.profile_command, os.path.join(ROOT, "profiles", args.profile_name),
+                      "rocprofv3 --pmc counter summary")
         return
     if args.trace_summary:
         trace_summary(args.trace_summary, args.profile_command, os.path.join(ROOT, "profiles", args.profile_name),
