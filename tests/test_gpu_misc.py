@@ -70,6 +70,24 @@ def test_tuning_does_not_change_output(tune):
     assert same_bits(ko, ek) and np.array_equal(po, ep)
 
 
+@pytest.mark.parametrize("dist", ["uniform", "deterdupl"])
+def test_three_levels_match_oracle(dist):
+    """Capacity 256 and target 128 leave 2^25 + 777 keys (more than 128 * 512^2)
+    three sample-sort levels of 64 buckets each (the multi-level sample sort
+    of Section 5 and Appendix G with l = 3); the output still equals the
+    oracle's."""
+    n = (1 << 25) + 777
+    x = gen.keys("u64", dist, n, seed=5)
+    ek, ep, _ = O.sort(x, threads=8)
+    with R.tuned(cap=256, target=128):
+        ws = torch.empty(R.plain_workspace_bytes(R.U64, n), dtype=torch.uint8, device="cuda")
+        banner("three levels %s" % dist)
+        ko, po = R.sort(dev(x), workspace=ws)
+        st = R.stats(ws)
+    assert st["status"] == 0 and st["levels"] == 3 and st["oversize"] >= 0
+    assert same_bits(host(ko), ek) and np.array_equal(host(po), ep)
+
+
 @pytest.mark.parametrize("log2_p,k,per_leaf", [(0, 2, 6), (3, 2, 2), (5, 4, 3), (8, 8, 2), (10, 2, 1), (6, 16, 5)])
 def test_median_tree_matches_oracle(log2_p, k, per_leaf):
     p = 1 << log2_p
