@@ -402,6 +402,37 @@ def bench_small(args, R, torch):
             "rows": rows}
 
 
+def bench_rquick_mw(args, R, torch):
+    """Robust hypercube quicksort over 2^log2_p workgroups (exchanges through
+    HBM) against the sample sort on the same single array: u32 keys, uniform
+    and all-equal, split by (key, position), by key only, and by the paper's
+    local choice among copies of the splitter key.  Reports the largest PE
+    part after the last exchange (load balance) next to the times."""
+    from gen import gen
+
+    rows = []
+    for n, lp in ((1 << 13, 2), (1 << 15, 3), (1 << 16, 4), (1 << 18, 5), (1 << 18, 6), (1 << 18, 8), (1 << 21, 8)):
+        for dist in ("uniform", "zero"):
+            x = torch.from_numpy(gen.keys("u32", dist, n, seed=1)).cuda()
+            ws = torch.empty(R.rquick_mw_workspace_bytes(n, lp), dtype=torch.uint8, device="cuda")
+            wsp = torch.empty(R.plain_workspace_bytes(R.U32, n), dtype=torch.uint8, device="cuda")
+            row = {"n": n, "log2_p": lp, "dist": dist}
+            for name, tb in (("rquick_tb", 1), ("rquick_ntb", 0), ("rquick_local", 2)):
+                t = _timed(torch, lambda: R.rquick_mw(x, lp, tie_break=tb, workspace=ws), args.steps, args.warmup)
+                row[name + "_us"] = round(t * 1e6, 1)
+                row[name + "_max_part"] = int(R.rquick_mw(x, lp, tie_break=tb, workspace=ws)[2][-1].item())
+            row["sample_sort_us"] = round(_timed(torch, lambda: R.sort(x, workspace=wsp), args.steps,
+                                                 args.warmup) * 1e6, 1)
+            row["n_over_p"] = n >> lp
+            rows.append(row)
+    ref = [r for r in rows if r["n"] == 1 << 18 and r["log2_p"] == 5 and r["dist"] == "uniform"][0]
+    return {"metric": "us per hypercube-quicksort of 2^18 u32 keys over 32 workgroups", "value": ref["rquick_tb_us"],
+            "unit": "us", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "one array of 2^13..2^21 u32 keys, uniform / all equal, 4..256 workgroups"},
+            "rows": rows}
+
+
 def bench_serving(args, R, torch):
     """Config 5: Poisson stream of sort requests through the sort server at
     0.5x and 0.8x of its measured closed-loop rate; sizes log-uniform in
@@ -643,7 +674,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n-log2", type=int, default=28)
-    ap.add_argument("--workload", default="plain", choices=["plain", "latency", "batched", "small", "serving"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "latency", "batched", "small", "serving",
+                                                             "rquick_mw"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-variant", default="1gib", choices=["1gib", "literal"])
     ap.add_argument("--requests", type=int, default=2000)
@@ -677,6 +709,8 @@ def main():
         out = bench_batched(args, R, torch)
     elif args.workload == "small":
         out = bench_small(args, R, torch)
+    elif args.workload == "rquick_mw":
+        out = bench_rquick_mw(args, R, torch)
     else:
         out = bench_serving(args, R, torch)
     if args.workload == "plain" and not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:

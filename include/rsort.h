@@ -75,6 +75,48 @@ int rsort_plain(rsort_key_t kt, const void *keys_in, uint64_t n, void *keys_out,
                 void *workspace, size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Robust hypercube quicksort with workgroups as PEs (paper Section 6,
+ * Algorithm 2) for one array, its exchanges going through HBM.  Sorts by the
+ * definition above (u32 or f32 keys only).
+ *
+ * p = 2^log2_p PEs (1 <= log2_p <= 8), each holding a packed part of the
+ * array.  Steps:
+ *   1. random redistribution (Section 3.1): in each of log2_p rounds every PE
+ *      keeps one random half of its part and sends the other half to its
+ *      partner across one cube dimension;
+ *   2. every PE sorts its part in LDS (at most 8192 keys: ceil(n / p) must
+ *      not exceed 8192);
+ *   3. for each dimension, highest first, the binary-tree median (Section
+ *      3.2, even window k, 2 <= k <= 16) of each subcube is its splitter;
+ *      PEs split their parts at it and exchange and merge halves.
+ * tie_break selects how a PE splits its sorted part at the splitter s:
+ *   1  by (key, position), as the robust sample sort orders elements: the
+ *      output is the definition above;
+ *   0  by key only (ablation without tie-breaking): the same output, only
+ *      the load balance differs (equal keys pile up on one side);
+ *   2  the paper's local scheme (Section 6): of the m copies of s's key in a
+ *      part a = a_l s^m a_r, keep x in L = a_l s^x with |L| closest to
+ *      |a| / 2.  keys_out is the sorted key sequence, but equal keys may
+ *      appear in any order, so perm_out is one valid sorting permutation,
+ *      not necessarily the one defined above.
+ * seed drives the shuffle and the median's coins.
+ *
+ *   keys_in   device u32/f32 [n]; keys_out device [n]; perm_out device u32
+ *             [n] or NULL.
+ *   load_out  device u32 [log2_p + 1] or NULL: the largest PE part after the
+ *             redistribution, then after each exchange round.
+ *   workspace rsort_rquick_mw_workspace(n, log2_p) bytes (0 = shape not
+ *             supported).
+ * Stream-ordered and asynchronous.  Errors: RSORT_EINVAL (key type, n >=
+ * 2^32 - 1, log2_p, k, tie_break, ceil(n / p) > 8192, NULL pointers with n > 0,
+ * overlapping buffers), RSORT_ENOMEM (workspace too small), RSORT_EDEVICE.
+ * ---------------------------------------------------------------------- */
+size_t rsort_rquick_mw_workspace(uint64_t n, uint32_t log2_p);
+int rsort_rquick_mw(rsort_key_t kt, const void *keys_in, uint64_t n, uint32_t log2_p, uint32_t k, int tie_break,
+                    uint64_t seed, void *keys_out, uint32_t *perm_out, uint32_t *load_out, void *workspace,
+                    size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Segmented (batched) sort: num_segs independent arrays in one call, each
  * sorted by the same definition with SEGMENT-LOCAL positions.  The work is a
  * fixed sequence of launches independent of num_segs; each segment is routed

@@ -78,6 +78,29 @@ int rsort_plain(rsort_key_t kt, const void* keys_in, uint64_t n, void* keys_out,
                                  workspace_bytes, (hipStream_t)stream));
 }
 
+size_t rsort_rquick_mw_workspace(uint64_t n, uint32_t log2_p) {
+  if (!rs::rquick_mw_shape_ok(n, log2_p, 2)) return 0;
+  return rs::rquick_mw_workspace(n, log2_p);
+}
+
+int rsort_rquick_mw(rsort_key_t kt, const void* keys_in, uint64_t n, uint32_t log2_p, uint32_t k, int tie_break,
+                    uint64_t seed, void* keys_out, uint32_t* perm_out, uint32_t* load_out, void* workspace,
+                    size_t workspace_bytes, void* stream) {
+  if ((kt != RSORT_U32 && kt != RSORT_F32) || !rs::rquick_mw_shape_ok(n, log2_p, k)) return RSORT_EINVAL;
+  if (tie_break < 0 || tie_break > 2) return RSORT_EINVAL;
+  if (n == 0) return RSORT_OK;
+  if (!keys_in || !keys_out || !workspace) return RSORT_EINVAL;
+  const uint64_t b = 4 * n, lb = 4ull * (log2_p + 1);
+  if (overlap(keys_in, b, keys_out, b) || overlap(keys_in, b, perm_out, b) || overlap(keys_out, b, perm_out, b) ||
+      overlap(workspace, workspace_bytes, keys_in, b) || overlap(workspace, workspace_bytes, keys_out, b) ||
+      overlap(workspace, workspace_bytes, perm_out, b) || overlap(workspace, workspace_bytes, load_out, lb) ||
+      overlap(load_out, lb, keys_out, b) || overlap(load_out, lb, perm_out, b))
+    return RSORT_EINVAL;
+  return map_rc(rs::enqueue_rquick_mw(kt == RSORT_F32, (const uint32_t*)keys_in, n, log2_p, k, tie_break, seed,
+                                      (uint32_t*)keys_out, perm_out, load_out, workspace, workspace_bytes,
+                                      (hipStream_t)stream));
+}
+
 size_t rsort_segmented_workspace(rsort_key_t kt, uint64_t n_total, uint32_t num_segs, int has_payload) {
   if (!valid_kt(kt) || n_total >= (1ull << 40)) return 0;
   return rs::workspace_bytes((int)kt, n_total, num_segs, has_payload != 0);

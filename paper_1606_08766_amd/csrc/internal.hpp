@@ -59,6 +59,13 @@ int enqueue_median_tree(const uint64_t* vals, uint64_t per_problem, const uint64
                         uint32_t k, const uint8_t* coins, uint32_t num_problems, uint64_t* out, void* ws,
                         size_t ws_bytes, hipStream_t st);
 
+// Hypercube quicksort with workgroups as PEs (rquick_mw.hip).
+bool rquick_mw_shape_ok(uint64_t n, uint32_t log2_p, uint32_t k);
+size_t rquick_mw_workspace(uint64_t n, uint32_t log2_p);
+int enqueue_rquick_mw(bool f32, const uint32_t* keys_in, uint64_t n, uint32_t log2_p, uint32_t k, int tie_break,
+                      uint64_t seed, uint32_t* keys_out, uint32_t* perm_out, uint32_t* load_out, void* ws,
+                      size_t ws_bytes, hipStream_t st);
+
 // One request of a packed batch (sort server): source keys, destination
 // keys / permutation, length and offset inside the packed arrays.
 struct BatchEntry {

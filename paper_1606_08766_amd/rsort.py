@@ -25,7 +25,8 @@ EXPORTS = [
     "rsort_segmented", "rsort_workspace_status", "rsort_stats", "rsort_get_tuning", "rsort_set_tuning",
     "rsort_server_create", "rsort_server_destroy", "rsort_submit", "rsort_poll", "rsort_wait", "rsort_release",
     "rsort_server_counters", "rsort_median_tree_workspace", "rsort_median_tree", "rsort_timing_begin",
-    "rsort_timing_end", "rsort_class_stats", "rsort_server_request_bytes",
+    "rsort_timing_end", "rsort_class_stats", "rsort_server_request_bytes", "rsort_rquick_mw_workspace",
+    "rsort_rquick_mw",
 ]
 
 
@@ -109,6 +110,10 @@ def lib():
         L.rsort_median_tree_workspace.argtypes = [u32, u32, u32]
         L.rsort_median_tree.restype = i32
         L.rsort_median_tree.argtypes = [vp, u64, vp, u32, u32, vp, u32, vp, vp, sz, vp]
+        L.rsort_rquick_mw_workspace.restype = sz
+        L.rsort_rquick_mw_workspace.argtypes = [u64, u32]
+        L.rsort_rquick_mw.restype = i32
+        L.rsort_rquick_mw.argtypes = [i32, vp, u64, u32, u32, i32, u64, vp, vp, vp, vp, sz, vp]
         _lib = L
     return _lib
 
@@ -314,6 +319,36 @@ def median_tree(vals: torch.Tensor, per_problem: int, leaf_off: torch.Tensor, lo
                                  _ptr(out), _ptr(ws), wsb, _stream(stream))
     _check(rc, "rsort_median_tree")
     return out.view(num_problems, 2)
+
+
+# ----------------------------------------------------------------------------- hypercube quicksort
+def rquick_mw_workspace_bytes(n: int, log2_p: int) -> int:
+    return int(lib().rsort_rquick_mw_workspace(n, log2_p))
+
+
+def rquick_mw(keys: torch.Tensor, log2_p: int, k: int = 16, tie_break=True, seed: int = 0x5EED,
+              with_perm: bool = True, kt=None, workspace: torch.Tensor | None = None, stream=None):
+    """Hypercube quicksort of one u32 / f32 array over 2^log2_p workgroups
+    (rsort_rquick_mw).  Returns (keys_out, perm_out or None, load) where
+    load[0] is the largest PE part after the redistribution and load[1 + r]
+    the largest after exchange round r (a device u32 tensor).  tie_break:
+    True / 1 = (key, position) split, False / 0 = key-only ablation,
+    "local" / 2 = the paper's local choice among copies of the splitter key
+    (sorted keys, equal keys in no fixed order)."""
+    mode = 2 if tie_break == "local" else int(tie_break)
+    _require_cuda(keys)
+    kt = _kt(keys, kt)
+    n = keys.numel()
+    ko = torch.empty_like(keys)
+    po = torch.empty(n, dtype=torch.uint32, device=keys.device) if with_perm else None
+    load = torch.zeros(log2_p + 1, dtype=torch.uint32, device=keys.device)
+    wsb = rquick_mw_workspace_bytes(n, log2_p)
+    if workspace is None:
+        workspace = torch.empty(max(wsb, 256), dtype=torch.uint8, device=keys.device)
+    rc = lib().rsort_rquick_mw(kt, _ptr(keys), n, log2_p, k, mode, seed & (2**64 - 1), _ptr(ko),
+                               _ptr(po), _ptr(load), _ptr(workspace), workspace.numel(), _stream(stream))
+    _check(rc, "rsort_rquick_mw")
+    return ko, po, load
 
 
 # ----------------------------------------------------------------------------- server

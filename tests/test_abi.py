@@ -51,6 +51,29 @@ def test_host_validation_without_gpu():
     assert R.strerror(R.ENOTFOUND) == "unknown ticket"
 
 
+def test_rquick_mw_host_validation_without_gpu():
+    """The hypercube quicksort's shape rules: u32/f32 keys only, 1 <= log2_p
+    <= 8, even window 2..16, at most 8192 keys per PE."""
+    L = R.lib()
+    vp = ctypes.c_void_p
+    ws = 1 << 30
+
+    def call(kt=R.U32, n=1000, log2_p=2, k=16, tb=1, kin=vp(1 << 20), kout=vp(1 << 24), wsb=ws):
+        return L.rsort_rquick_mw(kt, kin, n, log2_p, k, tb, 1, kout, None, None, vp(1 << 32), wsb, None)
+
+    assert call(n=0) == R.OK
+    assert call(kt=R.U64) == R.EINVAL
+    assert call(log2_p=0) == R.EINVAL and call(log2_p=9) == R.EINVAL
+    assert call(k=3) == R.EINVAL and call(k=0) == R.EINVAL and call(k=18) == R.EINVAL
+    assert call(n=8192 * 4 + 1, log2_p=2) == R.EINVAL  # a PE part above 8192 keys
+    assert call(tb=3) == R.EINVAL and call(tb=-1) == R.EINVAL
+    assert call(kin=None) == R.EINVAL
+    assert call(kout=vp((1 << 20) + 8)) == R.EINVAL  # overlapping input and output
+    assert call(wsb=R.rquick_mw_workspace_bytes(1000, 2) - 1) == R.ENOMEM
+    assert R.rquick_mw_workspace_bytes(8192 * 4, 2) > 2 * 8 * 8192 * 4
+    assert R.rquick_mw_workspace_bytes(8192 * 4 + 1, 2) == 0
+
+
 def test_workspace_sizes_monotone():
     for kt in (R.U32, R.U64, R.F32):
         prev = 0
