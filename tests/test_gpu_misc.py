@@ -88,6 +88,55 @@ def test_three_levels_match_oracle(dist):
     assert same_bits(host(ko), ek) and np.array_equal(host(po), ep)
 
 
+def _golden_rank_error():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "median_tree_rank_error.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    return {int(r[0]): (float(r[1]), float(r[2])) for r in rows}
+
+
+def test_median_tree_reproduces_figure4_on_device():
+    """Figure 4 (Appendix H) run on the device primitive over the whole
+    printed range up to n = 2^20: 2000 runs per n of random keys, two per
+    leaf, window k = 2.  Keys are 31-bit
+    random integers made distinct by their index in the low word.  The
+    maximal rank error and the mean squared rank error match the printed
+    curve: exactly where the worst case is near-certain (n <= 16), within
+    the spread of a maximum over 2000 runs elsewhere."""
+    gold = _golden_rank_error()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4)
+    runs = 2000
+    for lg in range(2, 21):
+        n = 1 << lg
+        p = n // 2
+        per_call = max(1, min(runs, (1 << 25) // n))
+        errs = []
+        done = 0
+        banner("figure 4 on device n=%d" % n)
+        while done < runs:
+            q = min(per_call, runs - done)
+            r = torch.randint(0, 1 << 31, (q, n), device="cuda", generator=g, dtype=torch.int64)
+            words = (r << 32) | torch.arange(n, device="cuda", dtype=torch.int64)
+            leaf_off = torch.arange(0, n + 1, 2, device="cuda", dtype=torch.int64).repeat(q)
+            coins = torch.randint(0, 2, (q * (p + 1),), device="cuda", generator=g, dtype=torch.uint8)
+            out = R.median_tree(words.reshape(-1).view(torch.uint64), n, leaf_off.view(torch.uint64), lg - 1, 2, coins,
+                                q)
+            side = out[:, 1].view(torch.int64)
+            assert int((side != 0).sum().item()) == 0
+            v = out[:, 0].view(torch.int64)
+            rank = (words < v[:, None]).sum(dim=1).double()
+            errs.append(((rank / (n - 1)) - 0.5).abs().cpu().numpy())
+            done += q
+        e = np.concatenate(errs)
+        gmax, gvar = gold[n]
+        if n <= 16:
+            assert e.max() == pytest.approx(gmax, abs=1e-6), n
+        else:
+            assert 0.7 * gmax <= e.max() <= 1.35 * gmax, (n, e.max(), gmax)
+        assert np.mean(e ** 2) == pytest.approx(gvar, rel=0.15), (n, np.mean(e ** 2), gvar)
+
+
 @pytest.mark.parametrize("log2_p,k,per_leaf", [(0, 2, 6), (3, 2, 2), (5, 4, 3), (8, 8, 2), (10, 2, 1), (6, 16, 5)])
 def test_median_tree_matches_oracle(log2_p, k, per_leaf):
     p = 1 << log2_p
@@ -198,12 +247,7 @@ def test_device_median_tree_reproduces_printed_rank_error(n):
     distinct uniform 32-bit integers, two per leaf, k = 2, random coins; the
     maximal rank error and the mean squared rank error land within the
     sampling error of the printed binary-tree curve."""
-    import os
-    gold = {}
-    for line in open(os.path.join(os.path.dirname(__file__), "golden", "median_tree_rank_error.txt")):
-        if line.strip() and not line.startswith("#"):
-            f = line.split()
-            gold[int(f[0])] = (float(f[1]), float(f[2]))
+    gold = _golden_rank_error()
     runs = 2000
     rng = np.random.default_rng(n)
     p = n // 2
