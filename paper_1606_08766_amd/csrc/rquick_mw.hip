@@ -40,8 +40,8 @@ namespace {
 constexpr uint32_t kMwCap = 8192;       // largest part a PE sorts in LDS
 constexpr uint32_t kMwMaxLog2P = 8;     // at most 256 PEs
 constexpr uint32_t kMwMaxK = 16;        // median window
-constexpr int kMwSizeThreads = 256;     // one thread per PE
 constexpr int kMwThreads = 256;
+static_assert((1u << kMwMaxLog2P) <= (uint32_t)kMwThreads, "a round's planning takes one thread per PE");
 
 // stream ids of the counter-based generator
 constexpr uint64_t kStShuffle = 0x5348554600000000ull, kStLeaf = 0x4C45414600000000ull,
@@ -93,27 +93,20 @@ __device__ __forceinline__ uint32_t split_point(const uint64_t* x, uint32_t m, c
   return half < below ? below : (half > upto ? upto : half);
 }
 
-// New part sizes and offsets for one exchange round over dimension j.
-// kMwShuffle: keep floor(m/2); otherwise split at the subcube's splitter as
-// the mode says.  split[i] = the size of PE i's
-// lower piece.  load_out (optional) receives the largest new part.
-__global__ __launch_bounds__(kMwSizeThreads) void k_mw_sizes(const uint64_t* D, const uint32_t* off, uint32_t P,
-                                                             uint32_t j, int mode, const MwPivot* piv,
-                                                             uint32_t* split, uint32_t* off_next,
-                                                             uint32_t* load_out) {
-  __shared__ uint32_t s_lo[kMwSizeThreads], s_m[kMwSizeThreads];
-  __shared__ uint32_t tmp[kMwSizeThreads / kWave + 1];
-  __shared__ uint32_t s_max;
+// Part sizes of one exchange round over dimension j, computed by every
+// workgroup of the round's kernel for all P PEs: s_lo[i] = the size of PE i's
+// lower piece (a shuffle keeps floor(m/2); a split round reads the split
+// points the splitter kernel stored), s_m[i] = its part size, s_off = the
+// exclusive scan of the new part sizes (s_off[P] = n), s_max = the largest.
+__device__ void plan_round(const uint32_t* off, uint32_t P, uint32_t j, const uint32_t* split, uint32_t* s_lo,
+                           uint32_t* s_m, uint32_t* s_off, uint32_t* tmp, uint32_t* s_max) {
+  const bool shuffle = split == nullptr;
   const uint32_t i = threadIdx.x;
-  if (i == 0) s_max = 0;
+  if (i == 0) *s_max = 0;
   uint32_t m = 0, lo = 0;
   if (i < P) {
     m = off[i + 1] - off[i];
-    if (mode == kMwShuffle)
-      lo = m / 2;
-    else
-      lo = split_point(D + off[i], m, piv[i >> (j + 1)], mode);
-    split[i] = lo;
+    lo = shuffle ? m / 2 : split[i];
   }
   s_lo[i] = lo;
   s_m[i] = m;
@@ -121,38 +114,50 @@ __global__ __launch_bounds__(kMwSizeThreads) void k_mw_sizes(const uint64_t* D, 
   uint32_t nm = 0;
   if (i < P) {
     const uint32_t q = i ^ (1u << j);
-    if (mode == kMwShuffle)
+    if (shuffle)
       nm = lo + (s_m[q] - s_lo[q]);
     else if (((i >> j) & 1u) == 0)
       nm = lo + s_lo[q];
     else
       nm = (m - lo) + (s_m[q] - s_lo[q]);
-    atomicMax(&s_max, nm);
+    atomicMax(s_max, nm);
   }
   uint32_t total = 0;
-  const uint32_t e = block_excl_scan<kMwSizeThreads>(nm, tmp, &total);
-  if (i < P) off_next[i] = e;
-  if (i == 0) off_next[P] = total;
+  const uint32_t e = block_excl_scan<kMwThreads>(nm, tmp, &total);
+  if (i < P) s_off[i] = e;
+  if (i == 0) s_off[P] = total;
   __syncthreads();
-  if (i == 0 && load_out) *load_out = s_max;
+}
+
+// The first workgroup of a round publishes the new offsets (read by the next
+// kernel) and the largest part.
+__device__ __forceinline__ void publish_round(const uint32_t* s_off, uint32_t s_max, uint32_t P, uint32_t* off_next,
+                                              uint32_t* load_out) {
+  if (blockIdx.x != 0 || blockIdx.y != 0) return;
+  for (uint32_t t = threadIdx.x; t <= P; t += blockDim.x) off_next[t] = s_off[t];
+  if (threadIdx.x == 0 && load_out) *load_out = s_max;
 }
 
 // Shuffle round j: PE i permutes its part by t -> (t*M + c) mod m (M a prime
 // above the part size, c random), keeps the first half and sends the second
-// behind its partner's kept half.
-__global__ __launch_bounds__(kMwThreads) void k_mw_shuffle_move(const uint64_t* D, const uint32_t* off,
-                                                                const uint32_t* split, const uint32_t* off_next,
-                                                                uint64_t* Dn, uint32_t n, uint32_t j,
-                                                                uint64_t seed) {
+// behind its partner's kept half.  Grid: (P, chunks of the part).
+__global__ __launch_bounds__(kMwThreads) void k_mw_shuffle(const uint64_t* D, const uint32_t* off,
+                                                           uint32_t* off_next, uint64_t* Dn, uint32_t n, uint32_t P,
+                                                           uint32_t j, uint64_t seed, uint32_t* load_out) {
+  __shared__ uint32_t s_lo[kMwThreads], s_m[kMwThreads], s_off[kMwThreads + 1];
+  __shared__ uint32_t tmp[kMwThreads / kWave + 1];
+  __shared__ uint32_t s_max;
+  plan_round(off, P, j, nullptr, s_lo, s_m, s_off, tmp, &s_max);
+  publish_round(s_off, s_max, P, off_next, load_out);
   const uint32_t i = blockIdx.x, q = i ^ (1u << j);
-  const uint32_t a = off[i], m = off[i + 1] - a;
+  const uint32_t a = off[i], m = s_m[i];
   if (m == 0) return;
-  const uint32_t h = split[i], hq = split[q];
+  const uint32_t h = s_lo[i];
   const uint64_t r = rand_at(seed, kStShuffle + j, i);
   constexpr uint32_t kPrimes[4] = {8209u, 8219u, 8221u, 8231u};  // all above kMwCap
   const uint64_t M = kPrimes[r & 3];
   const uint64_t c = (r >> 8) % m;
-  const uint32_t own = off_next[i], other = off_next[q] + hq;
+  const uint32_t own = s_off[i], other = s_off[q] + s_lo[q];
   for (uint32_t t = blockIdx.y * blockDim.x + threadIdx.x; t < m; t += gridDim.y * blockDim.x) {
     const uint32_t pi = (uint32_t)(((uint64_t)t * M + c) % m);
     const uint32_t dst = pi < h ? own + pi : other + (pi - h);
@@ -210,9 +215,11 @@ __device__ __forceinline__ bool mwin_less(const MwWin& x, const MwWin& y) {
 // middle by a coin when m is odd), entries outside the part being the
 // below-all / above-all sentinels; a node merges its children's windows and
 // forwards the middle k; the root returns entry k/2 or k/2 + 1 (1-based) of
-// its window by a coin.
+// its window by a coin.  The workgroup then stores every PE's split point
+// (the size of its lower piece) for the round's merge.
 __global__ __launch_bounds__(kMwThreads) void k_mw_pivot(const uint64_t* D, const uint32_t* off, uint32_t j,
-                                                         uint32_t k, uint64_t seed, MwPivot* piv) {
+                                                         uint32_t k, uint64_t seed, int mode, uint32_t* split) {
+  __shared__ MwPivot s_piv;
   __shared__ uint64_t wv[2][(1u << kMwMaxLog2P) * kMwMaxK];
   __shared__ uint32_t wc[2][(1u << kMwMaxLog2P) * kMwMaxK];
   const uint32_t q = blockIdx.x, S = 2u << j, first = q * S;
@@ -258,7 +265,13 @@ __global__ __launch_bounds__(kMwThreads) void k_mw_pivot(const uint64_t* D, cons
   if (threadIdx.x == 0) {
     const uint32_t c = (uint32_t)(rand_at(seed, kStRoot + j, q) & 1u);
     const uint32_t e = k / 2 - 1 + c;
-    piv[q] = MwPivot{wc[cur][e] == 1 ? wv[cur][e] : 0ull, wc[cur][e], 0};
+    s_piv = MwPivot{wc[cur][e] == 1 ? wv[cur][e] : 0ull, wc[cur][e], 0};
+  }
+  __syncthreads();
+  // every PE of the subcube splits its sorted part at the splitter
+  for (uint32_t l = threadIdx.x; l < S; l += blockDim.x) {
+    const uint32_t a = off[first + l], m = off[first + l + 1] - a;
+    split[first + l] = split_point(D + a, m, s_piv, mode);
   }
 }
 
@@ -278,17 +291,22 @@ __device__ __forceinline__ uint32_t count_below(const uint64_t* x, uint32_t m, u
   return lo;
 }
 
-__global__ __launch_bounds__(kMwThreads) void k_mw_merge(const uint64_t* D, const uint32_t* off,
-                                                         const uint32_t* split, const uint32_t* off_next,
-                                                         uint64_t* Dn, uint32_t n, uint32_t j) {
+__global__ __launch_bounds__(kMwThreads) void k_mw_split_merge(const uint64_t* D, const uint32_t* off,
+                                                               const uint32_t* split, uint32_t* off_next,
+                                                               uint64_t* Dn, uint32_t n, uint32_t P, uint32_t j,
+                                                               uint32_t* load_out) {
+  __shared__ uint32_t s_lo[kMwThreads], s_m[kMwThreads], s_off[kMwThreads + 1];
+  __shared__ uint32_t tmp[kMwThreads / kWave + 1];
+  __shared__ uint32_t s_max;
+  plan_round(off, P, j, split, s_lo, s_m, s_off, tmp, &s_max);
+  publish_round(s_off, s_max, P, off_next, load_out);
   const uint32_t i = blockIdx.x, q = i ^ (1u << j);
   const bool upper = ((i >> j) & 1u) != 0;
-  const uint32_t ai = off[i], mi = off[i + 1] - ai, si = split[i];
-  const uint32_t aq = off[q], mq = off[q + 1] - aq, sq = split[q];
-  const uint64_t* A = D + ai + (upper ? si : 0u);
-  const uint64_t* B = D + aq + (upper ? sq : 0u);
+  const uint32_t mi = s_m[i], si = s_lo[i], mq = s_m[q], sq = s_lo[q];
+  const uint64_t* A = D + off[i] + (upper ? si : 0u);
+  const uint64_t* B = D + off[q] + (upper ? sq : 0u);
   const uint32_t na = upper ? mi - si : si, nb = upper ? mq - sq : sq;
-  const uint32_t base = off_next[i];
+  const uint32_t base = s_off[i];
   for (uint32_t t = blockIdx.y * blockDim.x + threadIdx.x; t < na + nb; t += gridDim.y * blockDim.x) {
     const uint64_t v = t < na ? A[t] : B[t - na];
     const uint32_t dst = base + (t < na ? t + count_below(B, nb, v) : (t - na) + count_below(A, na, v));
@@ -311,7 +329,6 @@ struct MwLayout {
   uint64_t* D[2];
   uint32_t* off[2];
   uint32_t* split;
-  MwPivot* piv;
   size_t bytes;
 };
 
@@ -329,7 +346,6 @@ MwLayout mw_layout(char* base, uint64_t n, uint32_t P) {
   L.off[0] = (uint32_t*)take((P + 1) * 4);
   L.off[1] = (uint32_t*)take((P + 1) * 4);
   L.split = (uint32_t*)take(P * 4);
-  L.piv = (MwPivot*)take(P * sizeof(MwPivot));
   L.bytes = o;
   return L;
 }
@@ -363,19 +379,16 @@ int enqueue_rquick_mw(bool f32, const uint32_t* keys_in, uint64_t n64, uint32_t 
   const uint32_t chunks = (uint32_t)std::max<uint64_t>(1, (2 * ((n64 + P - 1) / P) + 2047) / 2048);
   int cur = 0;
   for (uint32_t j = 0; j < d; j++) {  // random redistribution
-    RS_LAUNCH(k_mw_sizes, 1, kMwSizeThreads, st, L.D[cur], L.off[cur], P, j, (int)kMwShuffle, L.piv, L.split, L.off[cur ^ 1],
-              (load_out && j + 1 == d) ? load_out : nullptr);
-    RS_LAUNCH(k_mw_shuffle_move, dim3(P, chunks), kMwThreads, st, L.D[cur], L.off[cur], L.split, L.off[cur ^ 1], L.D[cur ^ 1], n,
-              j, seed);
+    RS_LAUNCH(k_mw_shuffle, dim3(P, chunks), kMwThreads, st, L.D[cur], L.off[cur], L.off[cur ^ 1], L.D[cur ^ 1], n, P,
+              j, seed, (load_out && j + 1 == d) ? load_out : nullptr);
     cur ^= 1;
   }
   RS_LAUNCH(k_mw_sort, P, 1024, st, L.D[cur], L.off[cur], L.status);
   for (uint32_t r = 0; r < d; r++) {  // cube dimensions, highest first
     const uint32_t j = d - 1 - r;
-    RS_LAUNCH(k_mw_pivot, P >> (j + 1), kMwThreads, st, L.D[cur], L.off[cur], j, k, seed, L.piv);
-    RS_LAUNCH(k_mw_sizes, 1, kMwSizeThreads, st, L.D[cur], L.off[cur], P, j, (int)split_mode, L.piv, L.split,
-              L.off[cur ^ 1], load_out ? load_out + 1 + r : nullptr);
-    RS_LAUNCH(k_mw_merge, dim3(P, chunks), kMwThreads, st, L.D[cur], L.off[cur], L.split, L.off[cur ^ 1], L.D[cur ^ 1], n, j);
+    RS_LAUNCH(k_mw_pivot, P >> (j + 1), kMwThreads, st, L.D[cur], L.off[cur], j, k, seed, (int)split_mode, L.split);
+    RS_LAUNCH(k_mw_split_merge, dim3(P, chunks), kMwThreads, st, L.D[cur], L.off[cur], L.split, L.off[cur ^ 1],
+              L.D[cur ^ 1], n, P, j, load_out ? load_out + 1 + r : nullptr);
     cur ^= 1;
   }
   RS_LAUNCH(k_mw_out, grid, kMwThreads, st, L.D[cur], keys_in, n, keys_out, perm_out);
