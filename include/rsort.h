@@ -107,7 +107,11 @@ int rsort_plain(rsort_key_t kt, const void *keys_in, uint64_t n, void *keys_out,
  *             redistribution, then after each exchange round.
  *   workspace rsort_rquick_mw_workspace(n, log2_p) bytes (0 = shape not
  *             supported).
- * Stream-ordered and asynchronous.  Errors: RSORT_EINVAL (key type, n >=
+ * Stream-ordered and asynchronous.  A device-side guard sets the workspace
+ * status (rsort_workspace_status) to RSORT_EINVAL if a PE part ever exceeds
+ * 8192 keys before its LDS sort; the shuffle keeps every part within one key
+ * of ceil(n / p), so accepted shapes leave it at RSORT_OK.
+ * Errors: RSORT_EINVAL (key type, n >=
  * 2^32 - 1, log2_p, k, tie_break, ceil(n / p) > 8192, NULL pointers with n > 0,
  * overlapping buffers), RSORT_ENOMEM (workspace too small), RSORT_EDEVICE.
  * ---------------------------------------------------------------------- */

@@ -79,6 +79,18 @@ def test_rquick_mw_load_balance():
         assert load[-1] <= 1.5 * n / p, (dist, load)
 
 
+def test_rquick_mw_workspace_status_stays_ok():
+    """The LDS-capacity guard of the local sort never fires for accepted
+    shapes: the largest part is exactly ceil(n / p) after the shuffle."""
+    n, log2_p = (1 << 18) + 5, 6
+    x = gen.keys("u32", "uniform", n, seed=8)
+    ws = torch.empty(R.rquick_mw_workspace_bytes(n, log2_p), dtype=torch.uint8, device="cuda")
+    banner("rquick_mw workspace status")
+    _, _, load = R.rquick_mw(dev(x), log2_p, workspace=ws)
+    assert R.workspace_status(ws) == R.OK
+    assert int(host(load)[0]) <= -(-n // (1 << log2_p))
+
+
 def test_rquick_mw_seed_changes_nothing_in_the_output():
     n = (1 << 17) + 1
     x = gen.keys("u32", "deterdupl", n, seed=9)
