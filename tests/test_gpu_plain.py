@@ -93,6 +93,20 @@ def test_config2_full_size(dist):
         assert O.rank(x, int(po[r])) == int(r)
 
 
+@pytest.mark.parametrize("kt,dist", [("u32", "uniform"), ("u32", "gaussian"), ("f32", "uniform"), ("f32", "gaussian")])
+def test_full_size_32bit_keys(kt, dist):
+    """2^28 u32 and f32 keys (f32 uniform: random bit patterns with NaNs,
+    infinities and signed zeros), two sample-sort levels: the characterising
+    invariants plus ranks of sampled outputs computed by the oracle."""
+    n = 1 << 28
+    x = gen.keys(kt, dist, n, seed=3)
+    ko, po = gpu_sort(x)
+    check_sorted(x, ko, po)
+    rng = np.random.default_rng(11)
+    for r in rng.integers(0, n, 3):
+        assert O.rank(x, int(po[r])) == int(r)
+
+
 def test_repeat_calls_identical():
     x = gen.keys("u64", "gaussian", 3_000_000, seed=9)
     a = gpu_sort(x)
