@@ -129,15 +129,17 @@ def bench_plain(args, R, torch):
     from gen import gen
 
     n = 1 << args.n_log2
-    ks = 8
+    kt_name = args.key_type
+    kt = {"u64": R.U64, "u32": R.U32, "f32": R.F32}[kt_name]
+    ks = 8 if kt_name == "u64" else 4
     inputs = []
     for d in DISTS:
-        x = gen.keys("u64", d, n, seed=1)
+        x = gen.keys(kt_name, d, n, seed=1)
         inputs.append(torch.from_numpy(x).cuda())
         del x
     ko = torch.empty_like(inputs[0])
     po = torch.empty(n, dtype=torch.uint32, device="cuda")
-    ws = torch.empty(R.plain_workspace_bytes(R.U64, n), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(R.plain_workspace_bytes(kt, n), dtype=torch.uint8, device="cuda")
     if args.calib_copy_mib:
         # a plain device copy of known size, so that profiler byte counters
         # can be scaled by what they read for it
@@ -225,14 +227,15 @@ def bench_plain(args, R, torch):
         avg_s = dom_ms / dom_cnt / 1e3
         achieved = alg / avg_s / 1e9
         tr = None
-        if traffic and kernel_key(dom_name) in traffic.get("kernels", {}):
+        # the committed counters were taken on the u64 sort
+        if kt_name == "u64" and traffic and kernel_key(dom_name) in traffic.get("kernels", {}):
             tr = traffic["kernels"][kernel_key(dom_name)]["hbm_bytes_per_launch"]
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": dom_name,
                 "alg_bytes_per_launch": int(alg)}
     value = args.steps * n / elapsed / 1e9
     out = {
-        "metric": "Gkeys/s (plain multilevel sample sort, 2^%d u64 keys)" % args.n_log2,
+        "metric": "Gkeys/s (plain multilevel sample sort, 2^%d %s keys)" % (args.n_log2, kt_name),
         "value": round(value, 3),
         "unit": "Gkeys/s",
         "n_gpus": 1,
@@ -242,10 +245,10 @@ def bench_plain(args, R, torch):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64",
+        "dtype": kt_name,
         "data": "synthetic",
-        "config": {"workload": "plain sort of 2^%d uint64 keys, 2 levels x 256 buckets, distributions %s (steps "
-                               "cycle through them)" % (args.n_log2, "/".join(DISTS)),
+        "config": {"workload": "plain sort of 2^%d %s keys, %d levels, distributions %s (steps "
+                               "cycle through them)" % (args.n_log2, kt_name, int(st["levels"]), "/".join(DISTS)),
                    "n": n, "levels": int(st["levels"]), "key_bytes": ks, "perm": True},
         "roofline": roof,
         "passes": passes,
@@ -677,6 +680,7 @@ def main():
     ap.add_argument("--workload", default="plain", choices=["plain", "latency", "batched", "small", "serving",
                                                              "rquick_mw"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--key-type", default="u64", choices=["u64", "u32", "f32"], help="plain workload key type")
     ap.add_argument("--batched-variant", default="1gib", choices=["1gib", "literal"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
@@ -713,7 +717,8 @@ def main():
         out = bench_rquick_mw(args, R, torch)
     else:
         out = bench_serving(args, R, torch)
-    if args.workload == "plain" and not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
+    if (args.workload == "plain" and args.key_type == "u64" and not args.no_cpu_baseline
+            and int(os.environ.get("RANK", "0")) == 0):
         out["cpu_baseline"] = cpu_baseline(args.n_log2)
     print(json.dumps(out), flush=True)
 

@@ -45,10 +45,13 @@ __device__ __forceinline__ bool pair_less(K ka, uint32_t ia, K kb, uint32_t ib) 
 }
 
 template <typename K, bool F32>
-__device__ __forceinline__ K load_ord(const K* p, uint64_t i) {
-  K v = p[i];
+__device__ __forceinline__ K ord_of(K v) {
   if constexpr (F32) return (K)f32_ord((uint32_t)v);
   return v;
+}
+template <typename K, bool F32>
+__device__ __forceinline__ K load_ord(const K* p, uint64_t i) {
+  return ord_of<K, F32>(p[i]);
 }
 template <typename K, bool F32>
 __device__ __forceinline__ K to_output(K o) {

@@ -548,10 +548,16 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
         key[i] = K(0);
         if (valid[i]) {
           if constexpr (SRC_IN)
-            key[i] = load_ord<K, F32>(in_keys, base + jj);
+            key[i] = in_keys[base + jj];
           else
             key[i] = bv.key(base + jj);
         }
+      }
+      // f32 keys are mapped to their ordinals after all loads are issued (a
+      // map inside each guarded load would wait for that load first)
+      if constexpr (SRC_IN && F32) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) key[i] = ord_of<K, F32>(key[i]);
       }
       uint32_t b[ITEMS];
       const uint64_t ub = sc.ubase;
@@ -719,7 +725,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
         nb[i] = 0;
         if (jj < cnt) {
           if constexpr (SRC_IN) {
-            nkey[i] = load_ord<K, F32>(in_keys, base + jj);
+            nkey[i] = in_keys[base + jj];  // raw bits: mapped when the tile is used, so the prefetch does not wait
             nidx[i] = (uint32_t)(base + jj - bs.ubase);
           } else {
             bv.get(base + jj, nkey[i], nidx[i]);
@@ -739,7 +745,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         valid[i] = i * THREADS + threadIdx.x < cnt;
-        key[i] = nkey[i];
+        key[i] = SRC_IN ? ord_of<K, F32>(nkey[i]) : nkey[i];
         idx[i] = nidx[i];
         pay[i] = npay[i];
         b[i] = nb[i];
