@@ -233,7 +233,7 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
         const uint64_t r = rand_at(seed, ((uint64_t)lev << 40) ^ bs.start, j);
         const uint64_t pos = bs.start + (((r >> 32) * (uint64_t)bs.len) >> 32);
         if constexpr (SRC_IN) {
-          k[i] = load_ord<K, F32>(in_keys, pos);
+          k[i] = in_keys[pos];  // raw bits; mapped below once all loads are issued
           v[i] = (uint32_t)(pos - bs.ubase);
         } else {
           bv.get(pos, k[i], v[i]);
@@ -243,6 +243,11 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
         v[i] = kPadIdx;
       }
       p[i] = 0;
+    }
+    if constexpr (SRC_IN && F32) {
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++)
+        if (threadIdx.x * ITEMS + i < S) k[i] = ord_of<K, F32>(k[i]);
     }
     const uint32_t kk = 1u << bs.logk;
     // The splitters are the samples of rank j * ae - 1 (j = 1 .. kk - 1) in

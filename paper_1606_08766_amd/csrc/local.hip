@@ -88,7 +88,7 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
         if (f.src) {
           sb.get(f.start + j, k[i], v[i]);
         } else {
-          k[i] = load_ord<K, F32>(in_keys, f.start + j);
+          k[i] = in_keys[f.start + j];  // raw bits; mapped below once all loads are issued
           v[i] = j;
         }
       } else {
@@ -96,6 +96,13 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
         v[i] = kPadIdx;
       }
       p[i] = j;
+    }
+    if constexpr (F32) {
+      if (!f.src) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++)
+          if (i * THREADS + threadIdx.x < f.len) k[i] = ord_of<K, F32>(k[i]);
+      }
     }
     lds_merge_sort<K, THREADS, ITEMS, PAY>(k, v, p, sa);
 #pragma unroll
@@ -443,7 +450,7 @@ __global__ __launch_bounds__(THREADS) void k_oversize(Work w, const K* in_keys, 
           if (f.src) {
             sb.get(f.start + j, k[i], v[i]);
           } else {
-            k[i] = load_ord<K, F32>(in_keys, f.start + j);
+            k[i] = in_keys[f.start + j];  // raw bits; mapped below once all loads are issued
             v[i] = j;
           }
           p[i] = PAY ? srcp[f.start + j] : 0u;
@@ -451,6 +458,13 @@ __global__ __launch_bounds__(THREADS) void k_oversize(Work w, const K* in_keys, 
           k[i] = KMax<K>::v;
           v[i] = kPadIdx;
           p[i] = 0;
+        }
+      }
+      if constexpr (F32) {
+        if (!f.src) {
+#pragma unroll
+          for (int i = 0; i < ITEMS; i++)
+            if (c0 + threadIdx.x * ITEMS + i < f.len) k[i] = ord_of<K, F32>(k[i]);
         }
       }
       block_merge_sort<K, THREADS, ITEMS, PAY>(k, v, p, sk, sv, sp);
