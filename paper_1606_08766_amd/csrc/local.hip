@@ -84,18 +84,20 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
       // thread t takes logical elements t*ITEMS+i; load striped for coalescing
       // and let the first sort round place them (any input order is valid).
       const uint32_t j = i * THREADS + threadIdx.x;
-      if (j < f.len) {
-        if (f.src) {
-          sb.get(f.start + j, k[i], v[i]);
-        } else {
-          k[i] = in_keys[f.start + j];  // raw bits; mapped below once all loads are issued
-          v[i] = j;
-        }
-      } else {
-        k[i] = KMax<K>::v;
-        v[i] = kPadIdx;
-      }
+      k[i] = KMax<K>::v;
+      v[i] = j < f.len ? j : kPadIdx;
       p[i] = j;
+    }
+    // one source per segment (uniform), so each branch issues all its loads
+    // before any is used
+    if (f.src) {
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++)
+        if (i * THREADS + threadIdx.x < f.len) sb.get(f.start + i * THREADS + threadIdx.x, k[i], v[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++)
+        if (i * THREADS + threadIdx.x < f.len) k[i] = in_keys[f.start + i * THREADS + threadIdx.x];  // raw bits
     }
     if constexpr (F32) {
       if (!f.src) {
@@ -292,27 +294,40 @@ __global__ __launch_bounds__(THREADS, (THREADS >= 1024 ? 8 : 1)) void k_local_wo
     const uint32_t* srcp = f.src ? w.buf_pay[f.src - 1] : in_pay;
     auto idx_at = [&](uint32_t j) -> uint32_t { return (SRCBUF && f.src) ? s_idx[j] : j; };
     auto key_at = [&](uint32_t j) -> K { return f.src ? sb.key(f.start + j) : load_ord<K, F32>(in_keys, f.start + j); };
-    // thread t takes slots i*THREADS+t (striped, coalesced); keys wait in the
-    // word memory (not in registers) until the minimum is known
+    // thread t takes slots i*THREADS+t (striped, coalesced).  All ITEMS loads
+    // are issued before any is used: a use inside each guarded load would
+    // wait for that load before the next one goes out.  The keys then wait
+    // in the word memory until the minimum is known.
+    const bool from_buf = SRCBUF && f.src;
+    K kr[ITEMS];
+    uint32_t ir[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      kr[i] = K(0);
+      ir[i] = i * THREADS + tid;
+    }
+    if (from_buf) {  // uniform: one source per segment
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++)
+        if (i * THREADS + tid < f.len) sb.get(f.start + i * THREADS + tid, kr[i], ir[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++)
+        if (i * THREADS + tid < f.len) kr[i] = in_keys[f.start + i * THREADS + tid];
+    }
     K mn = KMax<K>::v, mx = K(0);
     uint32_t imn = ~0u, imx = 0u;
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = i * THREADS + tid;
       if (j < f.len) {
-        K key;
-        uint32_t idx = j;
-        if (SRCBUF && f.src) {
-          sb.get(f.start + j, key, idx);
-          s_idx[j] = idx;
-        } else {
-          key = load_ord<K, F32>(in_keys, f.start + j);
-        }
+        const K key = from_buf ? kr[i] : ord_of<K, F32>(kr[i]);
+        if (from_buf) s_idx[j] = ir[i];
         s_words[j] = (uint64_t)key;
         mn = key < mn ? key : mn;
         mx = key > mx ? key : mx;
-        imn = min(imn, idx);
-        imx = max(imx, idx);
+        imn = min(imn, ir[i]);
+        imx = max(imx, ir[i]);
       }
     }
     if constexpr (BINS) {
