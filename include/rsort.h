@@ -213,7 +213,11 @@ int rsort_set_tuning(const rsort_tuning *in);
  * error in a packed batch is reported to every request of that batch.
  *
  * Request buffers are device pointers owned by the caller and must stay
- * valid until rsort_poll returns something other than RSORT_PENDING.
+ * valid until rsort_poll returns something other than RSORT_PENDING.  The
+ * server's streams do not wait on any stream of the caller: keys_in must
+ * already hold its final contents on the device when rsort_submit is called
+ * (e.g. the producing stream has been synchronised), and keys_out / perm_out
+ * must not be read or written by other work until the ticket has finished.
  * Setting the environment variable RSORT_SERVER_LOG to a file path makes
  * each server append one line per launch (slot, requests, keys, host
  * enqueue time) and per completion to that file.
@@ -234,6 +238,12 @@ typedef struct {
   uint64_t t_start_ns;  /* admitted and enqueued */
   uint64_t t_done_ns;   /* completion observed by the server */
   uint32_t batch_size;  /* requests sorted in the same launch */
+  uint64_t dev_begin_ns; /* device timestamps of the start and the end of the */
+  uint64_t dev_end_ns;   /* launch sequence that sorted the request, in ns after an
+                            event the server records at creation (0 for the fake
+                            executor or on error); requests whose [begin, end)
+                            intervals intersect were in flight on the device at
+                            the same time */
 } rsort_result;
 
 /* Arena bytes one request of n keys takes when it runs alone (0 for n == 0

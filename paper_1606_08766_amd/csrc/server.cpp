@@ -125,12 +125,14 @@ struct Req {
   rsort_request r;
   int status = RSORT_PENDING;
   uint64_t t_submit = 0, t_start = 0, t_done = 0;
+  uint64_t dev_begin = 0, dev_end = 0;  // device timestamps, ns after the server's epoch event
   uint32_t batch = 1;
 };
 
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t event = nullptr;
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;  // timing events around the slot's work
   int32_t* status_host = nullptr;      // pinned
   rs::BatchEntry* tab_host = nullptr;  // pinned, kTabCap entries
   uint64_t* off_host = nullptr;        // pinned, kBatchMaxCount + 1 segment offsets
@@ -148,6 +150,7 @@ struct rsort_server {
   int device = 0;
   bool fake = false;
   char* arena_base = nullptr;  // device memory of the arena (null for the fake executor)
+  hipEvent_t epoch = nullptr;  // recorded once at creation: origin of the device timestamps
   Arena arena;
   std::mutex mu;
   std::condition_variable cv_sched, cv_done;
@@ -201,6 +204,7 @@ void rsort_server::launch(Slot& s, const std::vector<rsort_request>& group) {
   hipStream_t st = s.stream;
   char* base = arena_base + s.scratch_off;
   int rc = RSORT_OK;
+  if (hipEventRecord(s.ev_begin, st) != hipSuccess) rc = RSORT_EDEVICE;
   void* ws = nullptr;
   if (!s.small || group.size() == 1) {  // alone: no packing copies
     ws = base;
@@ -238,6 +242,7 @@ void rsort_server::launch(Slot& s, const std::vector<rsort_request>& group) {
   }
   if (rc == RSORT_OK && hipMemcpyAsync(s.status_host, ws, 4, hipMemcpyDeviceToHost, st) != hipSuccess)
     rc = RSORT_EDEVICE;
+  if (rc == RSORT_OK && hipEventRecord(s.ev_end, st) != hipSuccess) rc = RSORT_EDEVICE;
   s.launch_rc = rc;
   if (hipEventRecord(s.event, st) != hipSuccess && s.launch_rc == RSORT_OK) s.launch_rc = RSORT_EDEVICE;
 }
@@ -255,9 +260,20 @@ void rsort_server::complete(Slot& s) {
   const uint64_t t = now_ns();
   int st = s.launch_rc;
   if (st == RSORT_OK && !fake) st = *s.status_host;
+  uint64_t db = 0, de = 0;
+  if (st == RSORT_OK && !fake) {
+    float a = 0.f, b = 0.f;
+    if (hipEventElapsedTime(&a, epoch, s.ev_begin) == hipSuccess &&
+        hipEventElapsedTime(&b, epoch, s.ev_end) == hipSuccess) {
+      db = (uint64_t)((double)a * 1e6);
+      de = (uint64_t)((double)b * 1e6);
+    }
+  }
   for (uint64_t tk : s.tickets) {
     Req& r = reqs[tk];
     r.t_done = t;
+    r.dev_begin = db;
+    r.dev_end = de;
     r.status = st;
     // the fake executor fails exactly the requests marked as faulty
     if (fake && (uintptr_t)r.r.keys_in == kFakeFault) r.status = RSORT_EDEVICE;
@@ -376,12 +392,15 @@ static void destroy_server(rsort_server* s) {
     for (Slot& sl : s->slots) {
       if (sl.stream) (void)hipStreamSynchronize(sl.stream);
       if (sl.event) (void)hipEventDestroy(sl.event);
+      if (sl.ev_begin) (void)hipEventDestroy(sl.ev_begin);
+      if (sl.ev_end) (void)hipEventDestroy(sl.ev_end);
       if (sl.stream) (void)hipStreamDestroy(sl.stream);
       if (sl.status_host) (void)hipHostFree(sl.status_host);
       if (sl.off_host) (void)hipHostFree(sl.off_host);
       if (sl.tab_host) (void)hipHostFree(sl.tab_host);
     }
     if (s->arena_base) (void)hipFree(s->arena_base);
+    if (s->epoch) (void)hipEventDestroy(s->epoch);
   }
   delete s;
 }
@@ -415,6 +434,7 @@ int rsort_server_create(int device, uint64_t hbm_budget_bytes, uint32_t max_infl
     for (Slot& sl : s->slots) {
       if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&sl.event, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreate(&sl.ev_begin) != hipSuccess || hipEventCreate(&sl.ev_end) != hipSuccess ||
           hipHostMalloc((void**)&sl.status_host, 64, hipHostMallocDefault) != hipSuccess ||
           hipHostMalloc((void**)&sl.off_host, (kBatchMaxCount + 1) * 8, hipHostMallocDefault) != hipSuccess ||
           hipHostMalloc((void**)&sl.tab_host, kTabCap * sizeof(rs::BatchEntry), hipHostMallocDefault) !=
@@ -422,6 +442,11 @@ int rsort_server_create(int device, uint64_t hbm_budget_bytes, uint32_t max_infl
         destroy_server(s);
         return RSORT_EDEVICE;
       }
+    }
+    if (hipEventCreate(&s->epoch) != hipSuccess || hipEventRecord(s->epoch, s->slots[0].stream) != hipSuccess ||
+        hipEventSynchronize(s->epoch) != hipSuccess) {
+      destroy_server(s);
+      return RSORT_EDEVICE;
     }
   }
   if (const char* path = getenv("RSORT_SERVER_LOG")) {
@@ -480,6 +505,8 @@ static void fill(const Req& q, rsort_result* out) {
   out->t_start_ns = q.t_start;
   out->t_done_ns = q.t_done;
   out->batch_size = q.batch;
+  out->dev_begin_ns = q.dev_begin;
+  out->dev_end_ns = q.dev_end;
 }
 
 int rsort_poll(rsort_server* s, uint64_t ticket, rsort_result* out) {

@@ -16,7 +16,11 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librsort.so")
 
 U32, U64, F32 = 0, 1, 2
-KT_OF_DTYPE = {torch.uint32: U32, torch.int32: U32, torch.uint64: U64, torch.int64: U64, torch.float32: F32}
+# Key types by tensor dtype.  Signed integer tensors are not mapped: their
+# keys would be ordered by the unsigned bit pattern (negative after
+# positive), so they are rejected unless the caller passes kt explicitly.
+KT_OF_DTYPE = {torch.uint32: U32, torch.uint64: U64, torch.float32: F32}
+KEY_BYTES = {U32: 4, U64: 8, F32: 4}
 
 OK, PENDING, EINVAL, ENOMEM, EDEVICE, EBUSY, ENOTFOUND = 0, 1, -1, -2, -3, -4, -5
 
@@ -51,7 +55,8 @@ class Request(ctypes.Structure):
 
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("t_submit_ns", ctypes.c_uint64), ("t_start_ns", ctypes.c_uint64),
-                ("t_done_ns", ctypes.c_uint64), ("batch_size", ctypes.c_uint32)]
+                ("t_done_ns", ctypes.c_uint64), ("batch_size", ctypes.c_uint32),
+                ("dev_begin_ns", ctypes.c_uint64), ("dev_end_ns", ctypes.c_uint64)]
 
 
 _lib = None
@@ -141,7 +146,14 @@ def _ptr(t):
 
 def _kt(keys: torch.Tensor, kt=None) -> int:
     if kt is not None:
+        if kt not in KEY_BYTES:
+            raise ValueError("unknown key type %r" % (kt,))
+        if keys.element_size() != KEY_BYTES[kt]:
+            raise TypeError("key type %d needs %d-byte elements, got %s" % (kt, KEY_BYTES[kt], keys.dtype))
         return kt
+    if keys.dtype in (torch.int32, torch.int64):
+        raise TypeError("signed %s keys would be sorted by their unsigned bit pattern; pass uint32 / uint64 "
+                        "tensors, or kt=U32 / U64 to sort the bits as unsigned on purpose" % keys.dtype)
     if keys.dtype not in KT_OF_DTYPE:
         raise TypeError("unsupported key dtype %s" % keys.dtype)
     return KT_OF_DTYPE[keys.dtype]
@@ -151,6 +163,34 @@ def _require_cuda(*ts):
     for t in ts:
         if t is not None and (not t.is_cuda or not t.is_contiguous()):
             raise ValueError("tensors must be contiguous device tensors")
+
+
+def _require_like(t, name: str, device, numel: int, elem_bytes: int, dtypes=None):
+    """An output / side tensor the library reads or writes through a raw
+    pointer: on the keys' device, contiguous, of the right element size (and
+    dtype, if given) and length."""
+    if t is None:
+        return
+    if not t.is_cuda or not t.is_contiguous() or t.device != device:
+        raise ValueError("%s must be a contiguous tensor on %s" % (name, device))
+    if t.element_size() != elem_bytes or (dtypes is not None and t.dtype not in dtypes):
+        raise TypeError("%s has dtype %s" % (name, t.dtype))
+    if t.numel() != numel:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), numel))
+
+
+_U32_LIKE = (torch.uint32, torch.int32)
+
+
+def _keep_alive(stream, *ts):
+    """Tensors used by work enqueued on an explicitly given stream other than
+    the current one must not return to torch's caching allocator before that
+    work has run: record them on that stream."""
+    if stream is None or stream == torch.cuda.current_stream():
+        return
+    for t in ts:
+        if t is not None:
+            t.record_stream(stream)
 
 
 # ----------------------------------------------------------------------------- plain
@@ -164,19 +204,23 @@ def sort(keys: torch.Tensor, with_perm: bool = True, kt=None, workspace: torch.T
 
     Returns (keys_out, perm_out or None); perm_out[r] is the input position of
     the element of rank r (equal keys keep input order)."""
-    _require_cuda(keys)
     kt = _kt(keys, kt)
+    _require_cuda(keys)
     n = keys.numel()
     if out is not None:
         ko, po = out
     else:
         ko = torch.empty_like(keys)
         po = torch.empty(n, dtype=torch.uint32, device=keys.device) if with_perm else None
+    _require_like(ko, "keys_out", keys.device, n, keys.element_size())
+    _require_like(po, "perm_out", keys.device, n, 4, _U32_LIKE)
     wsb = plain_workspace_bytes(kt, n)
     if workspace is None:
         workspace = torch.empty(max(wsb, 256), dtype=torch.uint8, device=keys.device)
+    _require_cuda(workspace)
     rc = lib().rsort_plain(kt, _ptr(keys), n, _ptr(ko), _ptr(po), _ptr(workspace), workspace.numel(), _stream(stream))
     _check(rc, "rsort_plain")
+    _keep_alive(stream, keys, ko, po, workspace)
     return ko, po
 
 
@@ -192,22 +236,33 @@ def segmented_sort(keys: torch.Tensor, offsets: torch.Tensor, payload: torch.Ten
 
     offsets: device u64 (or int64) tensor of num_segs + 1 entries.  Returns
     (keys_out, perm_out or None, payload_out or None); perm is segment-local."""
-    _require_cuda(keys, offsets, payload)
     kt = _kt(keys, kt)
+    _require_cuda(keys, offsets, payload)
     n = keys.numel()
     ns = offsets.numel() - 1
+    if ns < 0:
+        raise ValueError("offsets needs num_segs + 1 >= 1 entries")
+    _require_like(offsets, "offsets", keys.device, ns + 1, 8, (torch.uint64, torch.int64))
+    _require_like(payload, "payload", keys.device, n, 4, _U32_LIKE)
     if out is not None:
         ko, po, plo = out
     else:
         ko = torch.empty_like(keys)
         po = torch.empty(n, dtype=torch.uint32, device=keys.device) if with_perm else None
         plo = torch.empty_like(payload) if payload is not None else None
+    _require_like(ko, "keys_out", keys.device, n, keys.element_size())
+    _require_like(po, "perm_out", keys.device, n, 4, _U32_LIKE)
+    _require_like(plo, "payload_out", keys.device, n, 4, _U32_LIKE)
+    if (payload is None) != (plo is None):
+        raise ValueError("payload and payload_out go together")
     wsb = segmented_workspace_bytes(kt, n, ns, payload is not None)
     if workspace is None:
         workspace = torch.empty(max(wsb, 256), dtype=torch.uint8, device=keys.device)
+    _require_cuda(workspace)
     rc = lib().rsort_segmented(kt, _ptr(keys), _ptr(payload), _ptr(offsets), ns, n, _ptr(ko), _ptr(plo), _ptr(po),
                                _ptr(workspace), workspace.numel(), _stream(stream))
     _check(rc, "rsort_segmented")
+    _keep_alive(stream, keys, offsets, payload, ko, po, plo, workspace)
     return ko, po, plo
 
 
@@ -376,6 +431,14 @@ class Server:
         return t.value
 
     def submit_tensors(self, keys: torch.Tensor, keys_out: torch.Tensor, perm_out: torch.Tensor | None, kt=None):
+        """Submit device tensors.  The server's streams do not wait on the
+        caller's stream, so the work that produced `keys` on the current
+        stream is waited for here (host synchronisation) before submitting."""
+        kt = _kt(keys, kt)
+        _require_cuda(keys)
+        _require_like(keys_out, "keys_out", keys.device, keys.numel(), keys.element_size())
+        _require_like(perm_out, "perm_out", keys.device, keys.numel(), 4, _U32_LIKE)
+        torch.cuda.current_stream(keys.device).synchronize()
         return self.submit(_kt(keys, kt), keys.data_ptr(), keys.numel(), keys_out.data_ptr(),
                            perm_out.data_ptr() if perm_out is not None else None)
 

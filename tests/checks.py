@@ -71,3 +71,57 @@ def closed_form(dist: str, n: int, dtype=np.uint64, distinct: int = 16):
         j = r - start[key.astype(np.int64)]
         return key.astype(dtype), (np.uint64(d) * j + key).astype(np.uint32)
     raise ValueError(dist)
+
+
+def check_sorted_segmented_device(keys, offsets, keys_out, perm, payload=None, payload_out=None,
+                                  chunk=1 << 27):
+    """The three characterising properties of ``check_sorted``, per segment,
+    evaluated with plain torch operations on device tensors (for inputs of
+    billions of keys, where host checks would take minutes):
+
+      1. perm maps every segment onto its own positions bijectively;
+      2. keys_out[r] == keys[start(r) + perm[r]] bit for bit (and payload);
+      3. (ord(keys_out[r]), perm[r]) strictly increases inside each segment.
+
+    keys/keys_out: u64 or u32 tensors (unsigned order; f32 is not handled
+    here); offsets: host numpy u64 array of num_segs + 1 entries; perm: u32."""
+    import torch
+
+    n = keys.numel()
+    dev = keys.device
+    assert keys_out.numel() == n and perm.numel() == n
+    if n == 0:
+        return
+    wide = keys.element_size() == 8
+    sdt = torch.int64 if wide else torch.int32
+    flip = torch.tensor(-(1 << 63) if wide else -(1 << 31), dtype=sdt, device=dev)
+    off = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int64)).to(dev)
+    lengths = off[1:] - off[:-1]
+    nseg = lengths.numel()
+    seg = torch.repeat_interleave(torch.arange(nseg, device=dev, dtype=torch.int32), lengths, output_size=n)
+    seen = torch.zeros(n, dtype=torch.bool, device=dev)
+    kin = keys.view(sdt)
+    kout = keys_out.view(sdt)
+    pin = perm.view(torch.int32)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        sg = seg[a:b].long()
+        p = pin[a:b].long() & 0xFFFFFFFF
+        assert bool((p < lengths[sg]).all()), "perm entry outside its segment near %d" % a
+        g = off[sg] + p
+        seen[g] = True
+        assert torch.equal(kout[a:b], kin[g]), "keys_out[r] != keys[start + perm[r]] near %d" % a
+        if payload is not None:
+            assert torch.equal(payload_out.view(torch.int32)[a:b], payload.view(torch.int32)[g]), \
+                "payload mismatch near %d" % a
+        lo = max(a - 1, 0)
+        o = kout[lo:b] ^ flip
+        q = pin[lo:b].long() & 0xFFFFFFFF
+        same = seg[lo + 1:b] == seg[lo:b - 1]
+        inc = (o[1:] > o[:-1]) | ((o[1:] == o[:-1]) & (q[1:] > q[:-1]))
+        bad = same & ~inc
+        if bool(bad.any()):
+            r = lo + int(torch.nonzero(bad)[0].item())
+            raise AssertionError("order violated between ranks %d and %d" % (r, r + 1))
+        del sg, p, g, o, q, same, inc, bad
+    assert bool(seen.all()), "perm is not a bijection on some segment"

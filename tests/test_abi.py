@@ -244,3 +244,26 @@ def test_autotune_save_load_roundtrip(tmp_path):
         assert (t.rfis_max, t.rquick_max, t.tile_log2, t.oversample, t.target) == (64, 2048, 13, 16, 3072)
     finally:
         R.set_tuning(**{f: getattr(saved, f) for f, _ in R.Tuning._fields_})
+
+
+def test_binding_rejects_signed_keys_and_bad_side_tensors():
+    """Signed integer keys would be ordered by their unsigned bit pattern
+    (negative after positive), so the binding refuses them unless the caller
+    names the unsigned key type on purpose; side tensors handed to the C ABI
+    as raw pointers are checked for size and element type first."""
+    import torch
+
+    for dt in (torch.int32, torch.int64):
+        x = torch.tensor([-3, 2, -1, 5], dtype=dt)
+        with pytest.raises(TypeError):
+            R.sort(x)
+        with pytest.raises(TypeError):
+            R.segmented_sort(x, torch.tensor([0, 4], dtype=torch.int64))
+    # an explicit key type of the wrong width is refused as well
+    with pytest.raises(TypeError):
+        R._kt(torch.zeros(4, dtype=torch.int32), R.U64)
+    assert R._kt(torch.zeros(4, dtype=torch.int64), R.U64) == R.U64
+    assert R._kt(torch.zeros(4, dtype=torch.float32)) == R.F32
+    cpu = torch.device("cpu")
+    with pytest.raises(ValueError):  # not a device tensor
+        R._require_like(torch.zeros(4, dtype=torch.uint32), "perm_out", cpu, 4, 4, R._U32_LIKE)

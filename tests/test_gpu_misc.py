@@ -100,9 +100,11 @@ def test_median_tree_reproduces_figure4_on_device():
     printed range up to n = 2^20: 2000 runs per n of random keys, two per
     leaf, window k = 2.  Keys are 31-bit
     random integers made distinct by their index in the low word.  The
-    maximal rank error and the mean squared rank error match the printed
-    curve: exactly where the worst case is near-certain (n <= 16), within
-    the spread of a maximum over 2000 runs elsewhere."""
+    maximal rank error matches the printed value exactly at n <= 16, where
+    the worst case is near-certain; for larger n the maximum of 2000 runs is
+    random, and the test asks only that it lies within -30 % / +35 % of the
+    printed value.  The mean squared rank error matches the printed
+    "variance" within 15 %."""
     gold = _golden_rank_error()
     g = torch.Generator(device="cuda")
     g.manual_seed(4)
@@ -187,6 +189,41 @@ def test_server_alone_equals_mix():
     assert max(r.batch_size for _, r in results) >= 1
     for (ak, ap), (ok, op) in zip(alone, outs):
         assert same_bits(ak, host(ok)) and np.array_equal(ap, host(op))
+
+
+def test_server_large_requests_overlap_and_are_exact():
+    """Requests up to 2^26 keys (config 5's largest), u32 / u64 / f32, go
+    through the server's large lane on separate streams: each output is the
+    unique sorted order (the characterising invariants, plus ranks of sampled
+    outputs from the definition), two of them are bit-identical to the same
+    request sorted alone, and the device intervals of at least two requests
+    intersect (their work was in flight on the GPU at the same time)."""
+    from tests.checks import check_sorted
+
+    specs = [("u64", "uniform", 1 << 26), ("u32", "gaussian", (1 << 26) - 5), ("f32", "uniform", (1 << 25) + 3),
+             ("u64", "deterdupl", (1 << 24) + 1), ("u32", "zero", 1 << 25), ("f32", "reverse", 3_000_001)]
+    reqs = [gen.keys(kt, d, n, seed=300 + i) for i, (kt, d, n) in enumerate(specs)]
+    alone = [gpu_sort(reqs[0]), gpu_sort(reqs[2])]
+    banner("server large lane, %d requests up to 2^26 keys" % len(reqs))
+    ins = [dev(x) for x in reqs]
+    outs = [(torch.empty_like(t), torch.empty(t.numel(), dtype=torch.uint32, device="cuda")) for t in ins]
+    with R.Server(device=0, hbm_budget_bytes=16 << 30, max_inflight=4) as s:
+        tickets = [s.submit_tensors(t, o[0], o[1]) for t, o in zip(ins, outs)]
+        results = [s.wait(t, 120000) for t in tickets]
+    assert all(rc == R.OK for rc, _ in results), [rc for rc, _ in results]
+    spans = [(r.dev_begin_ns, r.dev_end_ns) for _, r in results]
+    assert all(0 < b < e for b, e in spans), spans
+    overlap = any(max(spans[i][0], spans[j][0]) < min(spans[i][1], spans[j][1])
+                  for i in range(len(spans)) for j in range(i + 1, len(spans)))
+    assert overlap, spans
+    rng = np.random.default_rng(3)
+    for x, (ok, op) in zip(reqs, outs):
+        ko, po = host(ok), host(op)
+        check_sorted(x, ko, po)
+        for r in rng.integers(0, x.size, 2):
+            assert O.rank(x, int(po[r])) == int(r)
+    for (ak, ap), j in zip(alone, (0, 2)):
+        assert same_bits(ak, host(outs[j][0])) and np.array_equal(ap, host(outs[j][1]))
 
 
 def test_server_packed_small_requests_match_oracle():

@@ -1,12 +1,14 @@
 """Parity of rsort_segmented (size-class dispatch: RFIS, RQuick, LDS merge
 sort, sample-sort levels) against the oracle's per-segment sort."""
+import functools
+
 import numpy as np
 import pytest
 
 from gen import gen
 from oracle import oracle as O
 from paper_1606_08766_amd import rsort as R
-from tests.gpu_util import gpu_segmented, same_bits
+from tests.gpu_util import banner, dev, gpu_segmented, host, same_bits
 
 pytestmark = pytest.mark.gpu
 
@@ -14,6 +16,16 @@ ALGOS = {
     "default": dict(rfis_max=1024, rquick_max=4096),
     "merge_only": dict(rfis_max=1, rquick_max=1),
     "rquick_wide": dict(rfis_max=64, rquick_max=4096),
+}
+
+# Small-input regime at its own size: 2^14 independent arrays per call, so
+# every class kernel's workgroup sorts many arrays in turn (its grid is capped
+# at a few workgroups per CU) and LDS is reused from array to array.
+CONFIG3_ALGOS = {
+    "rfis": dict(rfis_max=1024, rquick_max=1),      # RFIS for n <= 1024
+    "rquick": dict(rfis_max=1, rquick_max=4096),    # RQuick for every class up to 4096
+    "words": dict(rfis_max=1, rquick_max=1),        # the LDS word sort everywhere
+    "production": {},                               # the library's default routing
 }
 
 
@@ -26,19 +38,33 @@ def check_against_oracle(keys, off, payload=None):
         assert np.array_equal(plo, epl)
 
 
-@pytest.mark.parametrize("algo", list(ALGOS))
-@pytest.mark.parametrize("n", [64, 256, 1024, 4096])
-@pytest.mark.parametrize("dist", ["uniform", "dup8"])
-def test_config3_small_arrays(algo, n, dist):
-    """Many independent arrays of equal size n, u32 keys (uniform or 8 distinct values)."""
-    count = 512
+@functools.lru_cache(maxsize=1)
+def _config3_case(n, dist):
+    """2^14 arrays of n u32 keys (uniform, or 8 distinct values) and the
+    oracle's per-array sort of them, computed once per (n, dist)."""
+    count = 1 << 14
     if dist == "uniform":
         keys = gen.keys("u32", "uniform", count * n, seed=1)
     else:
         keys = gen.keys("u32", "topbits", count * n, seed=1, param=3)
     off = np.arange(0, count * n + 1, n, dtype=np.uint64)
-    with R.tuned(**ALGOS[algo]):
-        check_against_oracle(keys, off)
+    ek, ep, _ = O.segmented(keys, off)
+    return keys, off, ek, ep
+
+
+@pytest.mark.parametrize("algo", list(CONFIG3_ALGOS))
+@pytest.mark.parametrize("dist", ["uniform", "dup8"])
+@pytest.mark.parametrize("n", [64, 256, 1024, 4096])
+def test_config3_small_arrays(algo, dist, n):
+    """Config 3 at full size: 2^14 independent arrays of n u32 keys (uniform or
+    8 distinct values), each class routed to RFIS (Section 5, Appendix F),
+    RQuick (Section 6, Algorithm 2) or the word sort; bit-exact against the
+    oracle's per-array sort."""
+    keys, off, ek, ep = _config3_case(n, dist)
+    with R.tuned(**CONFIG3_ALGOS[algo]):
+        ko, po, _, _ = gpu_segmented(keys, off)
+    assert same_bits(ko, ek)
+    assert np.array_equal(po, ep)
 
 
 RAGGED = [0, 1, 2, 3, 0, 63, 64, 65, 100, 255, 256, 257, 1000, 1024, 1025, 2048, 2049, 3000, 4096, 4097, 8192,
@@ -73,6 +99,42 @@ def test_config4_one_gib_variant():
     dists = gen.pick_dists(count, ["uniform", "zero", "deterdupl"], seed=2)
     keys, pay, off = gen.segmented("u64", sizes, dists, seed=3)
     check_against_oracle(keys, off, pay)
+
+
+def test_config4_literal_100k_segments_up_to_2p18():
+    """Config 4 as stated: 100k segments of log-uniform sizes in [1, 2^18]
+    (2.11e9 keys, about 17 GiB of u64 keys) with a random u32 payload,
+    Uniform / Zero / DeterDupl per segment, in one segmented call.  Too large
+    for the oracle as a whole: every segment is checked on the device for the
+    characterising properties (bijection onto its own positions, gather of
+    keys and payload, strictly increasing (key, position)), and 24 sampled
+    segments, including the largest, are compared element by element with
+    the oracle's sort of that segment alone."""
+    import torch
+
+    from tests.checks import check_sorted_segmented_device
+
+    count = 100_000
+    sizes = gen.log_uniform_sizes(count, 0, 18, seed=1)
+    dists = gen.pick_dists(count, ["uniform", "zero", "deterdupl"], seed=2)
+    keys, pay, off = gen.segmented("u64", sizes, dists, seed=3)
+    n = keys.size
+    banner("config 4 literal: %d segments, %d keys, with payload" % (count, n))
+    dk, dp = dev(keys), dev(pay)
+    ws = torch.empty(R.segmented_workspace_bytes(R.U64, n, count, True), dtype=torch.uint8, device="cuda")
+    ko, po, plo = R.segmented_sort(dk, dev(off.astype(np.uint64)), dp, workspace=ws)
+    assert R.workspace_status(ws) == R.OK
+    del ws
+    torch.cuda.synchronize()
+    check_sorted_segmented_device(dk, off, ko, po, dp, plo)
+    rng = np.random.default_rng(17)
+    pick = set(rng.choice(count, 23, replace=False).tolist()) | {int(np.argmax(sizes))}
+    for s in sorted(pick):
+        a, b = int(off[s]), int(off[s + 1])
+        ek, ep, epl = O.sort(keys[a:b], pay[a:b])
+        assert np.array_equal(host(ko[a:b]), ek), s
+        assert np.array_equal(host(po[a:b]), ep), s
+        assert np.array_equal(host(plo[a:b]), epl), s
 
 
 def test_single_big_segment_with_payload():

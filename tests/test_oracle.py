@@ -310,10 +310,12 @@ def _median_tree_rank_errors(n, runs, seed):
 def test_median_tree_reproduces_printed_rank_error_curve():
     """Figure 4 (Appendix H): 2000 runs per n on uniform 32-bit integers.  With
     two elements per leaf and k = 2 (the reading of the experiment's setup) the
-    oracle reproduces the printed maxima exactly where the worst case is hit
-    with certainty or near-certainty (n = 4, 8, 16, 128, 512), and the printed
-    "variance" as the mean squared rank error (the variance of r/(n-1) about
-    its expectation 1/2), within the sampling error of 2000 runs."""
+    oracle reproduces the printed maxima exactly at n = 4, 8 and 16, where the
+    worst case is hit with near-certainty in 2000 runs.  For n = 32 .. 2048 the
+    maximum of 2000 runs is itself a random quantity, and the test only asks
+    that it lies within -20 % / +25 % of the printed value.  The printed
+    "variance" is matched as the mean squared rank error (the variance of
+    r/(n-1) about its expectation 1/2), within 12 %."""
     gold = _golden_rank_error()
     for n in (4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048):
         errs = _median_tree_rank_errors(n, 2000, seed=1)
