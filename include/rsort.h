@@ -75,6 +75,26 @@ int rsort_plain(rsort_key_t kt, const void *keys_in, uint64_t n, void *keys_out,
                 void *workspace, size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * rsort_plain without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, hosts that
+ * forbid allocation while running).  Same sort, arguments and output as
+ * rsort_plain; the scratch is a 64 MiB device array that the library holds
+ * statically, one per GPU it runs on, until the process ends.  Nothing is
+ * allocated by the call.
+ *   n  must need at most 64 MiB of workspace, i.e.
+ *      rsort_plain_workspace(kt, n) <= 64 MiB: with the default tuning up to
+ *      about 2.5 million u64 keys or 3.1 million u32 / f32 keys; larger n
+ *      returns RSORT_ENOMEM before any device call.
+ * Calls on one GPU share its scratch array (each call resets what it uses):
+ * calls whose work overlaps on the same GPU (e.g. on two streams) race and
+ * must be ordered by the caller.
+ * Errors: as rsort_plain; RSORT_ENOMEM for n beyond the scratch;
+ * RSORT_EDEVICE if the scratch address cannot be obtained.
+ * ---------------------------------------------------------------------- */
+int rsort_plain_noalloc(rsort_key_t kt, const void *keys_in, uint64_t n, void *keys_out, uint32_t *perm_out,
+                        void *stream);
+
+/* ------------------------------------------------------------------------
  * Robust hypercube quicksort with workgroups as PEs (paper Section 6,
  * Algorithm 2) for one array, its exchanges going through HBM.  Sorts by the
  * definition above (u32 or f32 keys only).

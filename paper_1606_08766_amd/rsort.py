@@ -30,7 +30,7 @@ EXPORTS = [
     "rsort_server_create", "rsort_server_destroy", "rsort_submit", "rsort_poll", "rsort_wait", "rsort_release",
     "rsort_server_counters", "rsort_median_tree_workspace", "rsort_median_tree", "rsort_timing_begin",
     "rsort_timing_end", "rsort_class_stats", "rsort_server_request_bytes", "rsort_rquick_mw_workspace",
-    "rsort_rquick_mw",
+    "rsort_rquick_mw", "rsort_plain_noalloc",
 ]
 
 
@@ -117,6 +117,8 @@ def lib():
         L.rsort_median_tree.argtypes = [vp, u64, vp, u32, u32, vp, u32, vp, vp, sz, vp]
         L.rsort_rquick_mw_workspace.restype = sz
         L.rsort_rquick_mw_workspace.argtypes = [u64, u32]
+        L.rsort_plain_noalloc.restype = i32
+        L.rsort_plain_noalloc.argtypes = [i32, vp, u64, vp, vp, vp]
         L.rsort_rquick_mw.restype = i32
         L.rsort_rquick_mw.argtypes = [i32, vp, u64, u32, u32, i32, u64, vp, vp, vp, vp, sz, vp]
         _lib = L

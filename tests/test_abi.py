@@ -267,3 +267,14 @@ def test_binding_rejects_signed_keys_and_bad_side_tensors():
     cpu = torch.device("cpu")
     with pytest.raises(ValueError):  # not a device tensor
         R._require_like(torch.zeros(4, dtype=torch.uint32), "perm_out", cpu, 4, 4, R._U32_LIKE)
+
+
+def test_noalloc_refuses_sizes_beyond_its_scratch_without_gpu():
+    """rsort_plain_noalloc checks its size limit (64 MiB of workspace) before
+    any device call."""
+    n = 1 << 24
+    assert R.plain_workspace_bytes(R.U64, n) > (64 << 20)
+    rc = R.lib().rsort_plain_noalloc(R.U64, ctypes.c_void_p(16), n, ctypes.c_void_p(1 << 40), None, None)
+    assert rc == R.ENOMEM
+    assert R.lib().rsort_plain_noalloc(7, None, 5, None, None, None) == R.EINVAL
+    assert R.lib().rsort_plain_noalloc(R.U32, None, 0, None, None, None) == R.OK
