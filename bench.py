@@ -91,38 +91,80 @@ def kernel_class(name: str) -> str:
 
 def pass_bytes_per_key(ks: int):
     """Algorithmic HBM bytes per key of each pass (read + write) for keys of
-    ks bytes, u32 positions, (key, position) records in the level buffers and
-    levels of at most 256 buckets (one-byte bucket ids between the second
-    level's count and scatter)."""
+    ks bytes and u32 positions: every byte a pass must move, counted once.
+    The second level's count needs only the key (plus the position of a key
+    that ties a splitter key, not counted here); the bytes a record layout
+    or a bucket-id array adds on top show up in the measured traffic ratio."""
     return {
         "count_l1": ks,                 # read keys
-        "scatter_l1": ks + ks + 4,      # read keys; write (key, position) records
-        "count_l2": ks + 4 + 1,         # read records; write bucket id
-        "scatter_l2": 2 * (ks + 4) + 1,  # read records + bucket id; write records
-        "local_sort": 2 * (ks + 4),     # read records; write key + perm
+        "scatter_l1": ks + ks + 4,      # read keys; write (key, position)
+        "count_l2": ks,                 # read keys
+        "scatter_l2": 2 * (ks + 4),     # read and write (key, position)
+        "local_sort": 2 * (ks + 4),     # read (key, position); write key + perm
     }
 
 
-def cpu_baseline(n_log2: int, budget_s: float = 20.0):
-    """The oracle (std::sort of (key, position) records, multi-threaded) on a
-    bounded sample of the same workload."""
+def cpu_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def cpu_baseline(n_log2: int, budget_s: float = 25.0):
+    """The oracle (std::sort of (key, position) records) on a bounded sample
+    of the same workload: all host threads (chunk sorts + pairwise merges),
+    then one thread, over the five distributions."""
     from gen import gen
     from oracle import oracle as O
 
-    threads = max(1, min(os.cpu_count() or 1, 16))
+    model, nproc = cpu_info()
     m = 1 << min(n_log2, 24)
-    tot_keys, tot_t = 0, 0.0
-    for d in DISTS:
-        x = gen.keys("u64", d, m, seed=1)
-        t0 = time.perf_counter()
-        O.sort(x, threads=threads)
-        tot_t += time.perf_counter() - t0
-        tot_keys += m
-        if tot_t > budget_s:
-            break
-    return {"value": round(tot_keys / tot_t / 1e9, 4), "unit": "Gkeys/s", "cores": threads, "kind": "oracle",
-            "sample": "2^%d u64 keys per distribution over %s, std::sort of (key, position) records on %d "
-                      "threads with a pairwise merge tree" % (min(n_log2, 24), "/".join(DISTS), threads)}
+    xs = [gen.keys("u64", d, m, seed=1) for d in DISTS]
+    res = {}
+    for name, threads in (("all", nproc), ("one", 1)):
+        tot_keys, tot_t = 0, 0.0
+        for x in xs:
+            t0 = time.perf_counter()
+            O.sort(x, threads=threads)
+            tot_t += time.perf_counter() - t0
+            tot_keys += m
+            if tot_t > budget_s / 2:
+                break
+        res[name] = (tot_keys / tot_t / 1e9, tot_keys)
+    return {"value": round(res["all"][0], 4), "unit": "Gkeys/s", "cores": nproc, "kind": "oracle",
+            "sample": "2^%d u64 keys per distribution over %s (%d keys with all threads, %d with one), std::sort "
+                      "of (key, position) records, chunk sorts + pairwise merge tree on %d threads"
+                      % (min(n_log2, 24), "/".join(DISTS), res["all"][1], res["one"][1], nproc),
+            "single_thread_value": round(res["one"][0], 4), "cpu_model": model, "host_threads": nproc}
+
+
+def bandwidth_ceilings(R, torch, nbytes: int = 2 << 30, reps: int = 5):
+    """Rates of the library's own read-only and copy kernels over nbytes
+    (practical ceilings of a read pass and of a read + write pass)."""
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for kind, moved in (("read", nbytes), ("copy", 2 * nbytes)):
+        for _ in range(2):
+            R.bandwidth_probe(kind, src, dst, nbytes)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            R.bandwidth_probe(kind, src, dst, nbytes)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b) / reps
+        gbs = moved / (ms / 1e3) / 1e9
+        out[kind] = {"GB_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes": moved,
+                     "ms": round(ms, 4)}
+    del src, dst
+    return out
 
 
 def bench_plain(args, R, torch):
@@ -186,18 +228,28 @@ def bench_plain(args, R, torch):
         a["launches"] += cnt
         a["ms"] += ms
         a["kernels"].append(name)
+    traffic = load_traffic() if kt_name == "u64" and args.n_log2 == 28 else None
     passes = {}
     for c, a in agg.items():
         e = {"ms_per_sort": round(a["ms"] / args.steps, 4)}
         if c in bpk:
             gbs = bpk[c] * n / (a["ms"] / args.steps / 1e3) / 1e9
+            e["alg_bytes_per_key"] = bpk[c]
             e["GB_s"] = round(gbs, 1)
             e["frac"] = round(gbs / HBM_PEAK_GBS, 4)
+            if traffic:
+                # measured HBM bytes per sort (rocprofv3 FETCH_SIZE + WRITE_SIZE of
+                # every kernel of the pass) over the pass's algorithmic bytes
+                meas = 0.0
+                for k in a["kernels"]:
+                    kk = kernel_key(k)
+                    if kk in traffic["kernels"]:
+                        meas += traffic["kernels"][kk]["hbm_bytes_per_launch"] * timing[k][0] / args.steps
+                e["traffic_ratio"] = round(meas / (bpk[c] * n), 3) if meas else None
         passes[c] = e
     # dominant single kernel (by total time)
     dom_name, (dom_cnt, dom_ms) = max(timing.items(), key=lambda kv: kv[1][1])
     dom_class = kernel_class(dom_name)
-    traffic = load_traffic()
     roof = None
     if dom_class in bpk:
         # launches of this kernel per sort, and the keys one launch processes
@@ -227,8 +279,8 @@ def bench_plain(args, R, torch):
         avg_s = dom_ms / dom_cnt / 1e3
         achieved = alg / avg_s / 1e9
         tr = None
-        # the committed counters were taken on the u64 sort
-        if kt_name == "u64" and traffic and kernel_key(dom_name) in traffic.get("kernels", {}):
+        # the committed counters were taken on the 2^28 u64 sort
+        if traffic and kernel_key(dom_name) in traffic.get("kernels", {}):
             tr = traffic["kernels"][kernel_key(dom_name)]["hbm_bytes_per_launch"]
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": dom_name,
@@ -315,6 +367,21 @@ def bench_batched(args, R, torch):
     for name, (cnt, ms) in timing.items():
         c = kernel_class(name)
         per[c] = round(per.get(c, 0.0) + ms / calls, 4)
+    # algorithmic bytes per pass: keys of segments longer than the LDS
+    # capacity of a payload call (8192) take sample-sort levels
+    cap = 8192
+    n_lv = int(sizes[sizes > cap].sum())
+    n_in = n - n_lv
+    pass_bytes = {"count_l1": 8 * n_lv,                        # keys
+                  "scatter_l1": (8 + 4 + 12 + 4) * n_lv,       # key + payload in; record + payload out
+                  "local_sort": (8 + 4 + 16) * n_in + (12 + 4 + 16) * n_lv}  # in; key + payload + perm out
+    passes = {}
+    for c, ms in per.items():
+        e = {"ms_per_call": ms}
+        if c in pass_bytes and ms > 0 and pass_bytes[c]:
+            gbs = pass_bytes[c] / (ms / 1e3) / 1e9
+            e.update({"alg_bytes": pass_bytes[c], "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        passes[c] = e
     return {
         "metric": "Gkeys/s (batched segmented sort, %d segments)" % count,
         "value": round(batched, 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -324,7 +391,7 @@ def bench_batched(args, R, torch):
                                "Uniform/Zero/DeterDupl per segment" % hi, "n": n, "segments": count},
         "plain_per_segment_gkeys_s": round(plain, 3), "batched_over_plain": round(batched / plain, 2),
         "plain_sample": "rsort_plain on the first %d segments (%d keys), keys + perm only" % (m, npl),
-        "ms_per_pass": per,
+        "passes": passes, "keys_in_levels": n_lv,
     }
 
 
@@ -464,7 +531,7 @@ def bench_serving(args, R, torch):
     arena_k = torch.empty(ring, dtype=torch.uint64, device="cuda")
     arena_p = torch.empty(ring, dtype=torch.uint32, device="cuda")
     budget = 64 << 30
-    inflight = 16
+    inflight = args.serve_slots
 
     def run(qps):
         lat, keys, starts, ends = [], 0, [], []
@@ -548,6 +615,45 @@ def bench_serving(args, R, torch):
             "config": {"workload": "Poisson sort requests, sizes log-uniform [2^8, 2^26], key type uniform over "
                                    "u32/u64/f32, 5 distributions, 64 GiB budget, %d streams" % inflight},
             "serving": res}
+
+
+def run_extras(args, R, torch):
+    """The other configurations, run after the headline and reported as extra
+    keys of the same JSON line: 2^20-key latency, 2^14 small arrays, the
+    batched segmented sort (1 GiB and literal variants, each against one
+    plain sort per segment) and the serving loop (p50/p99 at 0.5x and 0.8x of
+    its saturation rate).  Progress goes to stderr."""
+    extras = {}
+
+    def step(name, fn):
+        t0 = time.perf_counter()
+        sys.stderr.write("[bench] %s ...\n" % name)
+        sys.stderr.flush()
+        r = fn()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        sys.stderr.write("[bench] %s done in %.1f s\n" % (name, time.perf_counter() - t0))
+        sys.stderr.flush()
+        return r
+
+    lat = step("config 1 latency", lambda: bench_latency(args, R, torch))
+    extras["config1_latency"] = {"us_mean": lat["value"], "p50_us": lat["p50_us"], "min_us": lat["min_us"],
+                                 "gkeys_s": lat["gkeys_per_s"], "sorts": lat["steps"], "config": lat["config"]}
+    sm = step("config 3 small arrays", lambda: bench_small(args, R, torch))
+    extras["config3_small"] = {"rows": sm["rows"], "best_gkeys_s_n4096": sm["value"], "config": sm["config"]}
+    b4 = {}
+    for variant in ("1gib", "literal"):
+        a = argparse.Namespace(**vars(args))
+        a.batched_variant = variant
+        r = step("config 4 batched (%s)" % variant, lambda: bench_batched(a, R, torch))
+        b4[variant] = {"gkeys_s": r["value"], "ms_per_call": r["ms_per_step"],
+                       "plain_per_segment_gkeys_s": r["plain_per_segment_gkeys_s"],
+                       "batched_over_plain": r["batched_over_plain"], "plain_sample": r["plain_sample"],
+                       "passes": r["passes"], "config": r["config"]}
+    extras["config4_batched"] = b4
+    sv = step("config 5 serving", lambda: bench_serving(args, R, torch))
+    extras["config5_serving"] = dict(sv["serving"], slots=args.serve_slots, config=sv["config"])
+    return extras
 
 
 def _read_pmc(path, counter):
@@ -683,6 +789,10 @@ def main():
     ap.add_argument("--key-type", default="u64", choices=["u64", "u32", "f32"], help="plain workload key type")
     ap.add_argument("--batched-variant", default="1gib", choices=["1gib", "literal"])
     ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--serve-slots", type=int, default=4,
+                    help="server streams (the GPU exposes 4 hardware queues per process by default)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="plain workload only: skip the ceilings and the other configurations")
     ap.add_argument("--serve-warmup", type=int, default=200)
     args = ap.parse_args()
     if args.pmc_summary:
@@ -717,6 +827,15 @@ def main():
         out = bench_rquick_mw(args, R, torch)
     else:
         out = bench_serving(args, R, torch)
+    if args.workload == "plain" and not args.no_extras:
+        torch.cuda.empty_cache()
+        out["ceilings"] = bandwidth_ceilings(R, torch)
+        cp = out["ceilings"]["copy"]["GB_s"]
+        rd = out["ceilings"]["read"]["GB_s"]
+        for c, e in out["passes"].items():
+            if "GB_s" in e:
+                e["frac_of_ceiling"] = round(e["GB_s"] / (rd if c.startswith("count") else cp), 4)
+        out.update(run_extras(args, R, torch))
     if (args.workload == "plain" and args.key_type == "u64" and not args.no_cpu_baseline
             and int(os.environ.get("RANK", "0")) == 0):
         out["cpu_baseline"] = cpu_baseline(args.n_log2)

@@ -75,6 +75,28 @@ int rsort_plain(rsort_key_t kt, const void *keys_in, uint64_t n, void *keys_out,
                 void *workspace, size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Plain sort with 64-bit positions, for arrays of 2^32 - 1 keys or more
+ * (n <= 2^36).  Same definition as rsort_plain with positions 0..n-1 as
+ * u64: perm_out (NULL = keys only) is a device u64 [n].
+ * One top level of the multilevel sample sort (Appendix G) splits the keys
+ * into 256 buckets by (key, 64-bit position) splitters with a stable scatter
+ * (each bucket keeps input order), then every bucket is sorted with 32-bit
+ * bucket-local positions -- which order equal keys as the global positions
+ * do -- and the permutation is gathered back to global positions.  Works for
+ * any n >= 0; below 2^32 - 1 keys rsort_plain is faster.
+ *   workspace  rsort_plain64_workspace(kt, n) bytes (about 34 B per u32 /
+ *              f32 key and 46 B per u64 key); its status word
+ *              (rsort_workspace_status) becomes RSORT_EINVAL if a bucket
+ *              reached 2^32 - 1 keys (keys too skewed for 256 buckets).
+ * Stream-ordered and asynchronous.  Errors: RSORT_EINVAL (kt, n > 2^36,
+ * NULL pointers with n > 0, overlapping buffers), RSORT_ENOMEM (workspace
+ * too small), RSORT_EDEVICE.
+ * ---------------------------------------------------------------------- */
+size_t rsort_plain64_workspace(rsort_key_t kt, uint64_t n);
+int rsort_plain64(rsort_key_t kt, const void *keys_in, uint64_t n, void *keys_out, uint64_t *perm_out,
+                  void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * rsort_plain without a workspace argument, for callers that cannot allocate
  * device memory (code under stream capture, tight serving loops, hosts that
  * forbid allocation while running).  Same sort, arguments and output as
@@ -303,6 +325,17 @@ int rsort_server_counters(rsort_server *s, uint64_t *queued, uint64_t *running,
 int rsort_timing_begin(void);
 int rsort_timing_end(uint32_t max_entries, char *names, uint32_t name_len, uint32_t *launches,
                      double *total_ms, uint32_t *n_entries);
+
+/* ------------------------------------------------------------------------
+ * Bandwidth probe (measurement support): kind 0 reads bytes of src once
+ * (16 bytes per lane per access) and writes one 32-bit word per workgroup to
+ * dst (at most 8 words per compute unit, so dst needs 8 * CUs * 4 bytes);
+ * kind 1 copies bytes of src to dst.  bytes and both pointers must be
+ * multiples of 16.  Stream-ordered; the rates these two reach are the
+ * practical ceilings of a read-only and of a read + write pass.
+ * Errors: RSORT_EINVAL (kind, alignment, NULL), RSORT_EDEVICE.
+ * ---------------------------------------------------------------------- */
+int rsort_bandwidth_probe(int kind, const void *src, void *dst, uint64_t bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * Binary-tree approximate median (paper Section 3.2), computed on the device

@@ -16,7 +16,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librsort.so")
 INCLUDE = os.path.join(os.path.dirname(PKG), "include")
 
-SOURCES = ["engine.hip", "local.hip", "small.hip", "median.hip", "rquick_mw.hip", "batch.hip", "noalloc.hip", "api.cpp",
+SOURCES = ["engine.hip", "local.hip", "small.hip", "median.hip", "rquick_mw.hip", "batch.hip", "noalloc.hip", "probe.hip", "wide.hip", "api.cpp",
            "server.cpp", "timing.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -78,6 +78,25 @@ int rsort_plain(rsort_key_t kt, const void* keys_in, uint64_t n, void* keys_out,
                                  workspace_bytes, (hipStream_t)stream));
 }
 
+size_t rsort_plain64_workspace(rsort_key_t kt, uint64_t n) {
+  if (!valid_kt(kt) || n > (1ull << 36)) return 0;
+  return rs::wide_workspace_bytes((int)kt, n);
+}
+
+int rsort_plain64(rsort_key_t kt, const void* keys_in, uint64_t n, void* keys_out, uint64_t* perm_out,
+                  void* workspace, size_t workspace_bytes, void* stream) {
+  if (!valid_kt(kt) || n > (1ull << 36)) return RSORT_EINVAL;
+  if (n == 0) return RSORT_OK;
+  if (!keys_in || !keys_out || !workspace) return RSORT_EINVAL;
+  const uint64_t kb = n * key_size(kt);
+  if (overlap(keys_in, kb, keys_out, kb) || overlap(keys_in, kb, perm_out, 8 * n) ||
+      overlap(keys_out, kb, perm_out, 8 * n) || overlap(workspace, workspace_bytes, keys_in, kb) ||
+      overlap(workspace, workspace_bytes, keys_out, kb) || overlap(workspace, workspace_bytes, perm_out, 8 * n))
+    return RSORT_EINVAL;
+  return map_rc(rs::enqueue_wide((int)kt, keys_in, n, keys_out, perm_out, workspace, workspace_bytes,
+                                 (hipStream_t)stream));
+}
+
 size_t rsort_rquick_mw_workspace(uint64_t n, uint32_t log2_p) {
   if (!rs::rquick_mw_shape_ok(n, log2_p, 2)) return 0;
   return rs::rquick_mw_workspace(n, log2_p);

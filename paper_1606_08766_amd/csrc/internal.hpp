@@ -53,6 +53,11 @@ template <typename K, bool F32, bool PAY>
 int launch_oversize(const Work& w, const K* kin, const uint32_t* pay_in, K* kout, uint32_t* perm_out,
                     uint32_t* pay_out, uint64_t cap_c, hipStream_t st);
 
+// Sort of up to 2^36 keys with 64-bit positions (wide.hip).
+size_t wide_workspace_bytes(int kt, uint64_t n);
+int enqueue_wide(int kt, const void* keys_in, uint64_t n, void* keys_out, uint64_t* perm_out, void* ws,
+                 size_t ws_bytes, hipStream_t st);
+
 // Device binary-tree median (median.hip).
 size_t median_tree_workspace(uint32_t log2_p, uint32_t k, uint32_t num_problems);
 int enqueue_median_tree(const uint64_t* vals, uint64_t per_problem, const uint64_t* leaf_off, uint32_t log2_p,

@@ -30,7 +30,8 @@ EXPORTS = [
     "rsort_server_create", "rsort_server_destroy", "rsort_submit", "rsort_poll", "rsort_wait", "rsort_release",
     "rsort_server_counters", "rsort_median_tree_workspace", "rsort_median_tree", "rsort_timing_begin",
     "rsort_timing_end", "rsort_class_stats", "rsort_server_request_bytes", "rsort_rquick_mw_workspace",
-    "rsort_rquick_mw", "rsort_plain_noalloc",
+    "rsort_rquick_mw", "rsort_plain_noalloc", "rsort_bandwidth_probe",
+    "rsort_plain64_workspace", "rsort_plain64",
 ]
 
 
@@ -117,6 +118,12 @@ def lib():
         L.rsort_median_tree.argtypes = [vp, u64, vp, u32, u32, vp, u32, vp, vp, sz, vp]
         L.rsort_rquick_mw_workspace.restype = sz
         L.rsort_rquick_mw_workspace.argtypes = [u64, u32]
+        L.rsort_plain64_workspace.restype = sz
+        L.rsort_plain64_workspace.argtypes = [i32, u64]
+        L.rsort_plain64.restype = i32
+        L.rsort_plain64.argtypes = [i32, vp, u64, vp, vp, vp, sz, vp]
+        L.rsort_bandwidth_probe.restype = i32
+        L.rsort_bandwidth_probe.argtypes = [i32, vp, vp, u64, vp]
         L.rsort_plain_noalloc.restype = i32
         L.rsort_plain_noalloc.argtypes = [i32, vp, u64, vp, vp, vp]
         L.rsort_rquick_mw.restype = i32
@@ -222,6 +229,34 @@ def sort(keys: torch.Tensor, with_perm: bool = True, kt=None, workspace: torch.T
     _require_cuda(workspace)
     rc = lib().rsort_plain(kt, _ptr(keys), n, _ptr(ko), _ptr(po), _ptr(workspace), workspace.numel(), _stream(stream))
     _check(rc, "rsort_plain")
+    _keep_alive(stream, keys, ko, po, workspace)
+    return ko, po
+
+
+def plain64_workspace_bytes(kt: int, n: int) -> int:
+    return int(lib().rsort_plain64_workspace(kt, n))
+
+
+def sort64(keys: torch.Tensor, with_perm: bool = True, kt=None, workspace: torch.Tensor | None = None,
+           out: tuple | None = None, stream=None):
+    """rsort_plain64: the same sort with 64-bit positions (any n up to 2^36).
+    Returns (keys_out, perm_out as a u64 tensor, or None)."""
+    kt = _kt(keys, kt)
+    _require_cuda(keys)
+    n = keys.numel()
+    if out is not None:
+        ko, po = out
+    else:
+        ko = torch.empty_like(keys)
+        po = torch.empty(n, dtype=torch.uint64, device=keys.device) if with_perm else None
+    _require_like(ko, "keys_out", keys.device, n, keys.element_size())
+    _require_like(po, "perm_out", keys.device, n, 8, (torch.uint64, torch.int64))
+    if workspace is None:
+        workspace = torch.empty(max(plain64_workspace_bytes(kt, n), 256), dtype=torch.uint8, device=keys.device)
+    _require_cuda(workspace)
+    rc = lib().rsort_plain64(kt, _ptr(keys), n, _ptr(ko), _ptr(po), _ptr(workspace), workspace.numel(),
+                             _stream(stream))
+    _check(rc, "rsort_plain64")
     _keep_alive(stream, keys, ko, po, workspace)
     return ko, po
 
@@ -359,6 +394,15 @@ def timing_end(max_entries: int = 128) -> dict:
         nm = raw[i * name_len:(i + 1) * name_len].split(b"\0", 1)[0].decode()
         out[nm] = (int(launches[i]), float(ms[i]))
     return out
+
+
+# ----------------------------------------------------------------------------- bandwidth probes
+def bandwidth_probe(kind: str, src: torch.Tensor, dst: torch.Tensor, nbytes: int, stream=None):
+    """Enqueue the library's read-only ("read") or copy ("copy") probe over
+    nbytes of src (see rsort_bandwidth_probe)."""
+    _require_cuda(src, dst)
+    rc = lib().rsort_bandwidth_probe({"read": 0, "copy": 1}[kind], _ptr(src), _ptr(dst), nbytes, _stream(stream))
+    _check(rc, "rsort_bandwidth_probe")
 
 
 # ----------------------------------------------------------------------------- median tree

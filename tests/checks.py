@@ -125,3 +125,38 @@ def check_sorted_segmented_device(keys, offsets, keys_out, perm, payload=None, p
             raise AssertionError("order violated between ranks %d and %d" % (r, r + 1))
         del sg, p, g, o, q, same, inc, bad
     assert bool(seen.all()), "perm is not a bijection on some segment"
+
+
+def check_sorted_device(keys, keys_out, perm, chunk=1 << 27):
+    """``check_sorted``'s three characterising properties for one array with
+    a 64-bit permutation, evaluated with plain torch operations on device
+    tensors (arrays of 2^32 keys and more): perm is a bijection on 0..n-1,
+    keys_out[r] == keys[perm[r]] bit for bit, and (ord(keys_out[r]), perm[r])
+    strictly increases.  keys: u64 or u32 tensors (unsigned order); perm: u64."""
+    import torch
+
+    n = keys.numel()
+    assert keys_out.numel() == n and perm.numel() == n
+    if n == 0:
+        return
+    dev = keys.device
+    wide = keys.element_size() == 8
+    sdt = torch.int64 if wide else torch.int32
+    flip = torch.tensor(-(1 << 63) if wide else -(1 << 31), dtype=sdt, device=dev)
+    kin, kout, p64 = keys.view(sdt), keys_out.view(sdt), perm.view(torch.int64)
+    seen = torch.zeros(n, dtype=torch.bool, device=dev)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        p = p64[a:b]
+        assert bool(((p >= 0) & (p < n)).all()), "perm entry out of range near %d" % a
+        seen[p] = True
+        assert torch.equal(kout[a:b], kin[p]), "keys_out[r] != keys[perm[r]] near %d" % a
+        lo = max(a - 1, 0)
+        o = kout[lo:b] ^ flip
+        q = p64[lo:b]
+        inc = (o[1:] > o[:-1]) | ((o[1:] == o[:-1]) & (q[1:] > q[:-1]))
+        if not bool(inc.all()):
+            r = lo + int(torch.nonzero(~inc)[0].item())
+            raise AssertionError("order violated between ranks %d and %d" % (r, r + 1))
+        del p, o, q, inc
+    assert bool(seen.all()), "perm is not a bijection"

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     src = open(os.path.join(ROOT, "include", "rsort.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(rsort_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(rsort_[a-z_0-9]+)\s*\(", src)))
 
 
 def test_library_exports_every_header_function():

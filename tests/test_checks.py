@@ -45,3 +45,29 @@ def test_device_checker_rejects_planted_mistakes(kt, mistake):
         plo[a + 1] = plo[a]
     with pytest.raises(AssertionError):
         check_sorted_segmented_device(keys, off, ko, po, pay, plo, chunk=97)
+
+
+@pytest.mark.parametrize("kt", ["u64", "u32"])
+def test_single_array_device_checker(kt):
+    """check_sorted_device (64-bit permutations) accepts the oracle's output
+    and rejects a swapped pair, a duplicated position and a wrong key."""
+    from tests.checks import check_sorted_device
+
+    x = gen.keys(kt, "deterdupl", 5000, seed=3)
+    ek, ep, _ = O.sort(x)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a))
+    keys, ko, po = t(x), t(ek), t(ep.astype(np.uint64))
+    check_sorted_device(keys, ko, po, chunk=333)
+    for mistake in ("swap", "dup", "key"):
+        k2, p2 = ko.clone(), po.clone()
+        if mistake == "swap":
+            k2[100], k2[4000] = ko[4000].clone(), ko[100].clone()
+            p2[100], p2[4000] = po[4000].clone(), po[100].clone()
+        elif mistake == "dup":
+            p2[101] = p2[100]
+            k2[101] = k2[100]
+        else:
+            kv = k2.view(torch.int64 if kt == "u64" else torch.int32)
+            kv[7] += 1
+        with pytest.raises(AssertionError):
+            check_sorted_device(keys, k2, p2, chunk=333)
