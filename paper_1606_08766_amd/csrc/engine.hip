@@ -36,9 +36,12 @@ static const uint32_t h_class_max[kNumClasses] = {64, 256, 1024, 2048, 3072, 409
 
 uint32_t class_max(int c) { return (c >= 0 && c < kNumClasses) ? h_class_max[c] : 0u; }
 
-__device__ __forceinline__ uint32_t class_of(uint32_t len, uint32_t cap, uint32_t force_fallback) {
+// cmin: the smallest class used.  A sort with few final buckets routes them
+// all to one or two large classes, so that they run in one launch that fills
+// the GPU instead of several nearly idle ones.
+__device__ __forceinline__ uint32_t class_of(uint32_t len, uint32_t cap, uint32_t force_fallback, uint32_t cmin) {
   if (len > cap || (force_fallback && len > 64)) return kNumClasses - 1;
-  uint32_t c = 0;
+  uint32_t c = cmin;
   while (len > c_class_max[c]) c++;
   return c;
 }
@@ -59,6 +62,12 @@ __device__ __forceinline__ uint32_t logk_for(uint32_t len, uint32_t target, uint
 }
 
 __device__ __forceinline__ void set_status(Ctl* ctl, int32_t code) { atomicCAS(&ctl->status, 0, code); }
+
+// The chained scan's per-chunk status words start at zero on every level.
+__device__ __forceinline__ void scan_flags_clear(const Work& w, uint32_t t, uint32_t nt) {
+  for (uint64_t i = t; i < w.scan_blocks; i += nt) w.scan_flags[i] = 0ull;
+}
+
 
 // Routing of a block's segments to the list of segments to split (index
 // kNumClasses) or to the final lists by size class, aggregated per block:
@@ -82,8 +91,9 @@ __device__ __forceinline__ void route_lds_init(RouteLds& L) {
 
 __device__ __forceinline__ void route(const Work& w, RouteLds& L, uint32_t* big_counter, BigSeg* big_list,
                                       bool active, bool to_big, uint64_t start, uint64_t ubase, uint32_t len,
-                                      uint32_t src, uint32_t cap, uint32_t ff, uint32_t target, uint32_t left) {
-  const uint32_t c = (active && !to_big) ? class_of(len, cap, ff) : 0u;
+                                      uint32_t src, uint32_t cap, uint32_t ff, uint32_t target, uint32_t left,
+                                      uint32_t cmin) {
+  const uint32_t c = (active && !to_big) ? class_of(len, cap, ff, cmin) : 0u;
   const uint32_t dest = to_big ? (uint32_t)kNumClasses : c;
   const uint32_t li = wave_append(L.cnt, dest, active);
   // keys per class (statistics): one LDS atomic per distinct class per wave
@@ -133,7 +143,7 @@ __global__ void k_reset(Ctl* ctl, uint32_t levels) {
 
 // Route every user segment: split it (big list 0) or sort it directly.
 __global__ void k_init(Work w, const uint64_t* seg_off, uint32_t num_segs, uint64_t n_total, uint32_t cap,
-                       uint32_t target, uint32_t levels, uint32_t ff) {
+                       uint32_t target, uint32_t levels, uint32_t ff, uint32_t cmin) {
   __shared__ RouteLds L;
   route_lds_init(L);
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -153,7 +163,39 @@ __global__ void k_init(Work w, const uint64_t* seg_off, uint32_t num_segs, uint6
     const uint32_t len = active ? (uint32_t)(b - a) : 0u;
     active = active && len > 0;
     route(w, L, &w.ctl->big_count[0], w.big[0], active, len > cap && levels > 0, a, a, len, 0u, cap, ff, target,
-          levels);
+          levels, cmin);
+  }
+}
+
+// A plain sort's start in one launch: reset the control block, route the one
+// segment [0, n) (split it, or sort it in its class), and plan level 0 when
+// it is split (one segment: its tile groups and count-matrix base are
+// immediate).
+__global__ __launch_bounds__(64) void k_start_plain(Work w, uint64_t n, uint32_t cap, uint32_t target,
+                                                   uint32_t levels, uint32_t ff, uint32_t cmin) {
+  uint32_t* p = reinterpret_cast<uint32_t*>(w.ctl);
+  const uint32_t nw = (uint32_t)(offsetof(Ctl, l0_spl_key) / 4);
+  for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) p[i] = (i == 1) ? levels : 0u;
+  if (levels > 0) scan_flags_clear(w, threadIdx.x, blockDim.x);
+  __syncthreads();
+  if (threadIdx.x != 0 || n == 0) return;
+  const uint32_t len = (uint32_t)n;
+  if (len > cap && levels > 0) {
+    const uint32_t logk = logk_for(len, target, levels);
+    w.big[0][0] = BigSeg{0ull, 0ull, len, logk};
+    const uint32_t ng = (uint32_t)((n + (1ull << w.group_log2) - 1) >> w.group_log2);
+    w.group_base[0] = 0;
+    w.group_base[1] = ng;
+    w.count_base[0] = 0;
+    w.count_base[1] = ng << logk;
+    w.ctl->big_count[0] = 1;
+    w.ctl->total_groups = ng;
+    w.ctl->total_counts = ng << logk;
+  } else {
+    const uint32_t c = class_of(len, cap, ff, cmin);
+    w.cls[c][0] = FinalSeg{0ull, len, 0u};
+    w.ctl->class_count[c] = 1;
+    w.ctl->class_keys[c] = n;
   }
 }
 
@@ -183,7 +225,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev) {
     cc += tc;
   }
   if (threadIdx.x < 16) w.ctl->queue[threadIdx.x >> 3][threadIdx.x & 7] = 0;
+  scan_flags_clear(w, threadIdx.x, kPlanThreads);
   if (threadIdx.x == 0) {
+    w.ctl->scan_next = 0;
     w.group_base[m] = ct;
     w.count_base[m] = cc;
     w.ctl->total_groups = ct;
@@ -606,9 +650,106 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive scan of counts[0 .. total_counts) into offsets (reduce-then-scan).
+// Exclusive scan of counts[0 .. total_counts) into offsets in one launch: a
+// chained scan with decoupled look-back.  Workgroups take chunks of
+// kScanChunk counts in order from a counter; each publishes its chunk's sum
+// at once and, after looking back at its predecessors' published sums (or
+// inclusive prefixes), its inclusive prefix.  A chunk's predecessors are held
+// by workgroups that are already running, so every wait ends; the wait is
+// bounded all the same (status set to an internal error after kScanSpinMax
+// polls).  Status word of chunk c: flag << 32 | value, flag 1 = the chunk's
+// sum, 2 = the inclusive prefix through the chunk; zeroed before each level.
+// Sums are taken modulo 2^32: offsets are only ever subtracted from offsets
+// of the same segment, which is shorter than 2^32.
 constexpr int kScanThreads = 256, kScanItems = 16, kScanChunk = kScanThreads * kScanItems;
+constexpr uint32_t kScanSpinMax = 1u << 26;
+constexpr uint64_t kChainedScanMax = 1u << 20;  // larger count matrices use reduce-then-scan
 
+__global__ __launch_bounds__(kScanThreads) void k_scan(Work w) {
+  __shared__ uint32_t tmp[kScanThreads / kWave + 1];
+  __shared__ uint32_t s_chunk, s_prefix;
+  const uint32_t M = w.ctl->total_counts;
+  const uint32_t nb = (M + kScanChunk - 1) / kScanChunk;
+  for (;;) {
+    if (threadIdx.x == 0) s_chunk = atomicAdd(&w.ctl->scan_next, 1u);
+    __syncthreads();
+    const uint32_t c = s_chunk;
+    if (c >= nb) break;
+    const uint32_t b0 = c * kScanChunk + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+#pragma unroll
+    for (int q = 0; q < kScanItems / 4; q++) {
+      const uint32_t j = b0 + 4 * q;
+      if (j + 4 <= M) {
+        const uint4 x = *reinterpret_cast<const uint4*>(w.counts + j);  // j % 4 == 0: 16-byte aligned
+        v[4 * q] = x.x;
+        v[4 * q + 1] = x.y;
+        v[4 * q + 2] = x.z;
+        v[4 * q + 3] = x.w;
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; r++) v[4 * q + r] = j + r < M ? w.counts[j + r] : 0u;
+      }
+    }
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) sum += v[i];
+    uint32_t tot;
+    uint32_t e = block_excl_scan<kScanThreads>(sum, tmp, &tot);
+    if (threadIdx.x == 0) {
+      uint32_t prefix = 0;
+      if (c == 0) {
+        __hip_atomic_store(&w.scan_flags[0], (2ull << 32) | tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        __hip_atomic_store(&w.scan_flags[c], (1ull << 32) | tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t j = c - 1, spins = 0;
+        for (;;) {
+          const uint64_t st =
+              __hip_atomic_load(&w.scan_flags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          const uint32_t flag = (uint32_t)(st >> 32);
+          if (flag == 0) {
+            if (++spins > kScanSpinMax) {
+              set_status(w.ctl, -3);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+          }
+          prefix += (uint32_t)st;
+          if (flag == 2 || j == 0) break;
+          j--;
+        }
+        __hip_atomic_store(&w.scan_flags[c], (2ull << 32) | (uint32_t)(prefix + tot), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+      s_prefix = prefix;
+    }
+    __syncthreads();
+    e += s_prefix;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+      const uint32_t x = v[i];
+      v[i] = e;
+      e += x;
+    }
+#pragma unroll
+    for (int q = 0; q < kScanItems / 4; q++) {
+      const uint32_t j = b0 + 4 * q;
+      if (j + 4 <= M) {
+        *reinterpret_cast<uint4*>(w.offsets + j) = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+          if (j + r < M) w.offsets[j + r] = v[4 * q + r];
+      }
+    }
+    __syncthreads();  // s_chunk / s_prefix are rewritten next
+  }
+}
+
+// Large count matrices: reduce-then-scan in three launches (partial sums of
+// chunks, a one-workgroup scan of the partials, the down-sweep), which for
+// thousands of chunks beats waiting on the chunks' predecessors.
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(Work w) {
   __shared__ uint32_t tmp[kScanThreads / kWave + 1];
   const uint32_t M = w.ctl->total_counts;
@@ -623,7 +764,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(Work w) {
     }
     uint32_t tot;
     block_excl_scan<kScanThreads>(s, tmp, &tot);
-    if (threadIdx.x == 0) w.partials[blk] = tot;
+    if (threadIdx.x == 0) w.scan_part[blk] = tot;
   }
 }
 
@@ -635,10 +776,10 @@ __global__ __launch_bounds__(kScanTopThreads) void k_scan_partials(Work w) {
   uint32_t carry = 0;
   for (uint32_t base = 0; base < nb; base += kScanTopThreads) {
     const uint32_t i = base + threadIdx.x;
-    const uint32_t v = i < nb ? w.partials[i] : 0u;
+    const uint32_t v = i < nb ? w.scan_part[i] : 0u;
     uint32_t tot;
     const uint32_t e = block_excl_scan<kScanTopThreads>(v, tmp, &tot);
-    if (i < nb) w.partials[i] = carry + e;
+    if (i < nb) w.scan_part[i] = carry + e;
     carry += tot;
   }
 }
@@ -656,7 +797,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(Work w) {
       v[i] = (base + i < M) ? w.counts[base + i] : 0u;
       s += v[i];
     }
-    uint32_t e = block_excl_scan<kScanThreads>(s, tmp, nullptr) + w.partials[blk];
+    uint32_t e = block_excl_scan<kScanThreads>(s, tmp, nullptr) + w.scan_part[blk];
 #pragma unroll
     for (int i = 0; i < kScanItems; i++) {
       if (base + i < M) w.offsets[base + i] = e;
@@ -671,8 +812,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(Work w) {
 template <typename K, bool F32, bool SRC_IN, bool PAY, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* in_keys, const uint32_t* in_pay,
                                                      int src_buf, int dst_buf) {
-  constexpr uint32_t TILE = THREADS * ITEMS;
-  static_assert(TILE <= (1u << kGroupMinLog2), "tiles divide a group");
+  constexpr uint32_t TILE = THREADS * ITEMS;  // the host launches tiles no larger than a group
   const uint32_t GT = (1u << w.group_log2) / TILE;  // tiles per group
   static_assert(THREADS >= kMaxK, "one histogram bin per thread");
   static_assert(TILE <= (1u << 23), "ranks fit 23 bits");
@@ -830,7 +970,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
 
 // Buckets of the finished level: split again or sort in LDS.
 __global__ void k_level_end(Work w, int lev, uint32_t cap, uint32_t target, int last, uint32_t dst_code,
-                            uint32_t ff, uint32_t left) {
+                            uint32_t ff, uint32_t left, uint32_t cmin) {
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
   const uint64_t total = (uint64_t)m * kMaxK;
@@ -871,7 +1011,7 @@ __global__ void k_level_end(Work w, int lev, uint32_t cap, uint32_t target, int 
     }
     active = active && len > 0;
     route(w, L, &w.ctl->big_count[cur ^ 1], w.big[cur ^ 1], active, len > cap && !last, bs.start + lo, bs.ubase,
-          len, dst_code, cap, ff, target, left);
+          len, dst_code, cap, ff, target, left, cmin);
   }
 }
 
@@ -943,13 +1083,15 @@ size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, 
   const uint64_t o_ti = take(big_max * kMaxK * 4);
   const uint64_t o_cnt = take(count_max * 4);
   const uint64_t o_off = take(count_max * 4);
-  const uint64_t o_par = take(scan_blocks * 4);
+  const uint64_t o_par = take(scan_blocks * 8);
+  const uint64_t o_part = take(scan_blocks * 4);
   uint64_t o_cls[kNumClasses], cls_cap[kNumClasses];
   for (int c = 0; c < kNumClasses; c++) {
     const uint64_t lo = c == 0 ? 0 : h_class_max[c - 1];
     uint64_t bound = n / (lo + 1) + 1;
     if (c == kNumClasses - 1) bound = n / (std::min<uint64_t>(cap, 64) + 1) + 1;
-    cls_cap[c] = std::min<uint64_t>(final_max, bound);
+    // a single-level plain sort may route all its (at most kMaxK) buckets to one class
+    cls_cap[c] = std::min<uint64_t>(final_max, std::max<uint64_t>(bound, kMaxK + 1));
     o_cls[c] = take(cls_cap[c] * sizeof(FinalSeg));
   }
   const uint64_t nb = (levels || t.force_fallback) ? n : 0;
@@ -969,7 +1111,8 @@ size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, 
     w->tree_idx = (uint32_t*)(base + o_ti);
     w->counts = (uint32_t*)(base + o_cnt);
     w->offsets = (uint32_t*)(base + o_off);
-    w->partials = (uint32_t*)(base + o_par);
+    w->scan_flags = (uint64_t*)(base + o_par);
+    w->scan_part = (uint32_t*)(base + o_part);
     for (int c = 0; c < kNumClasses; c++) {
       w->cls[c] = (FinalSeg*)(base + o_cls[c]);
       w->cls_cap[c] = cls_cap[c];
@@ -1049,20 +1192,38 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
     while (n > h_class_max[c]) c++;
     return launch_class_sort<K, F32, PAY>(c | kDirect, w, kin, pay_in, kout, perm_out, pay_out, 1, st, t);
   }
-  RS_LAUNCH(k_reset, 1, 256, st, w.ctl, levels);
-  RS_LAUNCH(k_init, grid_for((num_segs + 1023) / 1024, 1), 1024, st, w, seg_off, num_segs, n, cap, target, levels,
-            ff);
+  // A single-level plain sort with at most about two final buckets per CU
+  // routes all of them to the class kernel for twice the target size (and
+  // the one above it), so the local sorts run in one or two launches.
+  uint32_t cmin = 0;
+  if (!seg_off && levels == 1 && n <= (uint64_t)target * 2 * num_cu()) {
+    const uint32_t want = std::min<uint32_t>(2 * target, cap);
+    while (cmin + 2 < (uint32_t)kNumClasses && h_class_max[cmin] < want) cmin++;
+  }
+  if (!seg_off) {
+    RS_LAUNCH(k_start_plain, 1, 64, st, w, n, cap, target, levels, ff, cmin);
+  } else {
+    RS_LAUNCH(k_reset, 1, 256, st, w.ctl, levels);
+    RS_LAUNCH(k_init, grid_for((num_segs + 1023) / 1024, 1), 1024, st, w, seg_off, num_segs, n, cap, target, levels,
+              ff, cmin);
+  }
 
-  const uint32_t tile_log2 = t.tile_log2 == 12 ? 12 : 13;
+  // scatter tiles are at most a tile group
+  const uint32_t tile_log2 = (t.tile_log2 == 12 || w.group_log2 < 13) ? 12 : 13;
   const uint64_t groups_max = (n >> w.group_log2) + w.big_max + 1;
   for (uint32_t lev = 0; lev < levels; lev++) {
     const int dst = lev & 1;
     const int src = (lev + 1) & 1;  // buffer written by the previous level
     const bool last = lev + 1 == levels;
-    RS_LAUNCH(k_plan, 1, kPlanThreads, st, w, (int)lev);
+    if (lev > 0 || seg_off) RS_LAUNCH(k_plan, 1, kPlanThreads, st, w, (int)lev);  // level 0 of a plain sort: planned at the start
     const uint32_t gs = grid_for(w.big_max, 4);
     if (lev == 0) {
-      RS_LAUNCH((k_splitters<K, F32, true, kSplThreads, kSplItems>), gs, kSplThreads, st, w, (int)lev, kin, src, a, t.seed);
+      // a single-level sort of few buckets (cmin > 0) is latency-bound on its
+      // one-workgroup sample sort: 16 samples per bucket keep its buckets
+      // within twice the target while halving that step
+      const uint32_t a0 = cmin ? std::min<uint32_t>(a, 16u) : a;
+      RS_LAUNCH((k_splitters<K, F32, true, kSplThreads, kSplItems>), gs, kSplThreads, st, w, (int)lev, kin, src, a0,
+                t.seed);
     } else {
       RS_LAUNCH((k_splitters<K, false, false, kSplThreads, kSplItems>), gs, kSplThreads, st, w, (int)lev, kin, src, a,
                 t.seed);
@@ -1077,10 +1238,14 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
       RS_LAUNCH((k_count<K, F32, true, 512, 8>), gt, 512, st, w, (int)lev, kin, src);
     else
       RS_LAUNCH((k_count<K, false, false, 512, 8>), gt, 512, st, w, (int)lev, kin, src);
-    const uint32_t gsc = grid_for(w.count_max / kScanChunk + 1, 8);
-    RS_LAUNCH(k_scan_reduce, gsc, kScanThreads, st, w);
-    RS_LAUNCH(k_scan_partials, 1, kScanTopThreads, st, w);
-    RS_LAUNCH(k_scan_down, gsc, kScanThreads, st, w);
+    if (w.count_max <= kChainedScanMax) {
+      RS_LAUNCH(k_scan, grid_for(w.count_max / kScanChunk + 1, 4), kScanThreads, st, w);
+    } else {
+      const uint32_t gsc = grid_for(w.count_max / kScanChunk + 1, 8);
+      RS_LAUNCH(k_scan_reduce, gsc, kScanThreads, st, w);
+      RS_LAUNCH(k_scan_partials, 1, kScanTopThreads, st, w);
+      RS_LAUNCH(k_scan_down, gsc, kScanThreads, st, w);
+    }
     if (tile_log2 == 12) {
       if (lev == 0)
         RS_LAUNCH((k_scatter<K, F32, true, PAY, 512, 8>), gs_sc, 512, st, w, (int)lev, kin, pay_in, src, dst);
@@ -1093,12 +1258,12 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
         RS_LAUNCH((k_scatter<K, false, false, PAY, 1024, 8>), gs_sc, 1024, st, w, (int)lev, kin, pay_in, src, dst);
     }
     RS_LAUNCH(k_level_end, grid_for((w.big_max * kMaxK + 255) / 256, 4), 256, st, w, (int)lev, cap, target,
-              last ? 1 : 0, (uint32_t)(dst + 1), ff, levels - lev - 1);
+              last ? 1 : 0, (uint32_t)(dst + 1), ff, levels - lev - 1, cmin);
   }
 
   // final segments by size class (a class can only be non-empty if its lower
   // bound is below cap)
-  for (int c = 0; c < kNumClasses - 1; c++) {
+  for (int c = (int)cmin; c < kNumClasses - 1; c++) {
     if (c > 0 && h_class_max[c - 1] >= cap) break;
     const int kinds = levels == 0 ? kInputOnly : (num_segs > 1 ? kMixed : 0);
     const int rc = launch_class_sort<K, F32, PAY>(c | kinds, w, kin, pay_in, kout, perm_out, pay_out, w.cls_cap[c],

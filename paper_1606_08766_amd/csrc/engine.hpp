@@ -17,7 +17,7 @@ constexpr uint32_t kMaxOversample = 32;
 // that the groups of n keys occupy the whole GPU), each by one workgroup;
 // histograms and offsets are kept per (bucket, group), so the count and
 // scatter passes may use different tile sizes inside a group.
-constexpr uint32_t kGroupMinLog2 = 13, kGroupMaxLog2 = 17;
+constexpr uint32_t kGroupMinLog2 = 12, kGroupMaxLog2 = 17;
 
 // A segment that the current level splits.
 struct BigSeg {
@@ -45,6 +45,8 @@ struct Ctl {
   uint32_t big_count[2];           // ping-pong lists of segments to split
   uint32_t total_groups;           // tile groups of the current level
   uint32_t total_counts;           // entries of the current level's count matrix
+  uint32_t scan_next;              // next chunk of the count matrix to scan (chained scan)
+  uint32_t pad_scan;
   uint32_t queue[2][8];            // per-XCD tile-group queues of the count and scatter passes
   uint32_t class_count[kNumClasses];  // final segments per size class (last = oversize)
   uint32_t level_max[kMaxLevels];  // largest bucket created per level
@@ -68,7 +70,8 @@ struct Work {
   uint32_t* tree_idx;
   uint32_t* counts;      // [count_max]
   uint32_t* offsets;     // [count_max]
-  uint32_t* partials;    // [scan_blocks + 1]
+  uint64_t* scan_flags;  // [scan_blocks] chained-scan status of each chunk of the count matrix
+  uint32_t* scan_part;   // [scan_blocks] chunk sums of the reduce-then-scan
   FinalSeg* cls[kNumClasses];     // per size class lists
   uint64_t cls_cap[kNumClasses];
   uint32_t* buf_rec[2];  // A, B: [n] element records (ordinal key, position; see BufView)
