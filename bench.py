@@ -443,6 +443,8 @@ def bench_small(args, R, torch):
     algos = {"rfis": dict(rfis_max=1024, rquick_max=1), "rquick": dict(rfis_max=1, rquick_max=4096),
              "merge": dict(rfis_max=1, rquick_max=1)}
     for n in (64, 256, 1024, 4096):
+        if args.small_n and n != args.small_n:
+            continue
         for dist in ("uniform", "dup8"):
             x = gen.keys("u32", "uniform" if dist == "uniform" else "topbits", arrays * n, seed=1,
                          param=0 if dist == "uniform" else 3)
@@ -452,6 +454,8 @@ def bench_small(args, R, torch):
             ws = torch.empty(R.segmented_workspace_bytes(R.U32, dx.numel(), arrays, False), dtype=torch.uint8,
                              device="cuda")
             for a, tune in algos.items():
+                if args.small_algo and a != args.small_algo:
+                    continue
                 if a == "rfis" and n > 1024:
                     continue
                 if a == "rquick" and n < 2048:
@@ -464,7 +468,7 @@ def bench_small(args, R, torch):
                 if a == "rfis":
                     row["compares_per_s"] = float("%.4g" % (arrays * n * n / t))
                 rows.append(row)
-    best = max(r["gkeys_s"] for r in rows if r["n"] == 4096)
+    best = max([r["gkeys_s"] for r in rows if r["n"] == 4096] or [0.0])
     return {"metric": "Gkeys/s (2^14 small arrays, best algorithm at n = 4096)", "value": best, "unit": "Gkeys/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "u32", "data": "synthetic",
@@ -788,6 +792,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--key-type", default="u64", choices=["u64", "u32", "f32"], help="plain workload key type")
     ap.add_argument("--batched-variant", default="1gib", choices=["1gib", "literal"])
+    ap.add_argument("--small-n", type=int, default=0, help="small workload: only this array size")
+    ap.add_argument("--small-algo", default="", choices=["", "rfis", "rquick", "merge"],
+                    help="small workload: only this algorithm")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=4,
                     help="server streams (the GPU exposes 4 hardware queues per process by default)")
