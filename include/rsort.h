@@ -233,6 +233,14 @@ typedef struct {
   uint32_t tile_log2;    /* log2 of keys per scatter tile (12 or 13; counting uses 12) */
   uint32_t force_fallback; /* debug: 1 = every final bucket > 64 takes the
                               global-memory fallback sort, 2 = off (0 keeps) */
+  uint32_t extra_levels;   /* levels beyond the fewest that reach the target
+                              bucket size (at most 4): more, smaller levels
+                              shorten nothing but lengthen each scatter's runs;
+                              the value is stored plus one (1 = none, 0 keeps) */
+  uint32_t class_shape;    /* bit c set: final-size class c (0..8) runs its word
+                              sort with the alternative workgroup shape (twice
+                              the threads, half the keys per thread) -- bit 31
+                              must be set for the mask to be taken (0 keeps) */
 } rsort_tuning;
 
 int rsort_get_tuning(rsort_tuning *out);

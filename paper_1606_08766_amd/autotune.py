@@ -10,8 +10,11 @@ times the candidates on the current GPU and sets the library's tuning:
   the two thresholds the library understands (classes with upper bound
   <= rfis_max use RFIS, classes <= rquick_max use RQuick, larger ones the
   merge sort), picked to minimise the summed per-key time over the classes;
-* tile size, oversampling and target bucket size of the sample-sort levels,
-  timed on a plain sort.
+* per final-size class from 1024 to 4096 keys, the word sort's workgroup
+  shape (the default, or twice the threads with half the keys per thread),
+  expressed as the class_shape bit mask;
+* tile size, oversampling, target bucket size and the number of sample-sort
+  levels (the fewest that reach the target, or one more) of a plain sort.
 
 Results are plain JSON (``save``/``load``); ``apply`` installs them with
 ``rsort_set_tuning``.  Tuning changes speed only: every setting produces the
@@ -29,6 +32,8 @@ CLASS_BOUNDS = (64, 256, 1024, 2048, 3072, 4096, 6144, 8192, 12288)
 RFIS_BOUNDS = (64, 256, 1024)
 RQUICK_BOUNDS = (2048, 3072, 4096)
 ALGOS = ("rfis", "rquick", "merge")
+ALT_SHAPE_BOUNDS = (1024, 2048, 3072, 4096)  # classes with an alternative word-sort shape
+SHAPE_ON = 0x80000000  # class_shape is taken only with bit 31 set
 
 
 def algo_for(bound: int, rfis_max: int, rquick_max: int) -> str:
@@ -102,37 +107,51 @@ def tune(kt: str = "u64", quick: bool = False, seg_keys: int = 1 << 22, n_plain:
             ws = torch.empty(R.segmented_workspace_bytes(ktc, dk.numel(), count, False), dtype=torch.uint8,
                              device="cuda")
             out = (torch.empty_like(dk), torch.empty(dk.numel(), dtype=torch.uint32, device="cuda"), None)
-            for algo in ALGOS:
+            for algo in ALGOS + ("merge_alt",):
                 if algo == "rfis" and bound not in RFIS_BOUNDS:
                     continue
                 if algo == "rquick" and bound not in RQUICK_BOUNDS:
                     continue
+                if algo == "merge_alt" and bound not in ALT_SHAPE_BOUNDS:
+                    continue
                 rf = bound if algo == "rfis" else 1
                 rq = bound if algo == "rquick" else 1
-                R.set_tuning(**dict(keep, rfis_max=rf, rquick_max=rq))
+                cs = SHAPE_ON | ((1 << CLASS_BOUNDS.index(bound)) if algo == "merge_alt" else 0)
+                R.set_tuning(**dict(keep, rfis_max=rf, rquick_max=rq, class_shape=cs))
                 ms = _time_ms(torch, lambda: R.segmented_sort(dk, offs, workspace=ws, out=out), iters)
                 times[(bound, algo)] = ms * 1e6 / dk.numel()
             del dk, ws, out
-        rf, rq, _ = choose_thresholds(times)
+        # the word sort of a class takes its faster shape
+        shape = 0
+        for b in ALT_SHAPE_BOUNDS:
+            if times.get((b, "merge_alt"), float("inf")) < times.get((b, "merge"), float("inf")):
+                shape |= 1 << CLASS_BOUNDS.index(b)
+                times[(b, "merge")] = times[(b, "merge_alt")]
+        rf, rq, _ = choose_thresholds({k: v for k, v in times.items() if k[1] != "merge_alt"})
         # --- sample-sort levels on a plain sort
         x = torch.from_numpy(gen.keys(kt, "uniform", n_plain, seed=7)).cuda()
         ws = torch.empty(R.plain_workspace_bytes(ktc, n_plain), dtype=torch.uint8, device="cuda")
         out = (torch.empty_like(x), torch.empty(n_plain, dtype=torch.uint32, device="cuda"))
-        grid = list(itertools.product((12, 13), (16, 32), (4096, 5120, 6144)))
+        grid = list(itertools.product((12, 13), (16, 32), (4096, 5120, 6144), (0, 1)))
         if quick:
             grid = grid[:3]
         level = {}
-        for tl, a, tg in grid:
-            R.set_tuning(**dict(keep, rfis_max=rf, rquick_max=rq, tile_log2=tl, oversample=a, target=tg))
-            level[(tl, a, tg)] = _time_ms(torch, lambda: R.sort(x, workspace=ws, out=out), iters)
-        tl, a, tg = min(level, key=level.get)
+        for tl, a, tg, ex in grid:
+            R.set_tuning(**dict(keep, rfis_max=rf, rquick_max=rq, tile_log2=tl, oversample=a, target=tg,
+                                extra_levels=ex + 1, class_shape=SHAPE_ON | shape))
+            wsb = R.plain_workspace_bytes(ktc, n_plain)
+            if wsb > ws.numel():
+                ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+            level[(tl, a, tg, ex)] = _time_ms(torch, lambda: R.sort(x, workspace=ws, out=out), iters)
+        tl, a, tg, ex = min(level, key=level.get)
     finally:
         R.set_tuning(**keep)
     result = {
         "key_type": kt,
         "rfis_max": rf, "rquick_max": rq, "tile_log2": tl, "oversample": a, "target": tg,
+        "extra_levels": ex, "class_shape": shape,
         "class_ns_per_key": {"%d/%s" % k: round(v, 4) for k, v in sorted(times.items())},
-        "plain_ms": {"%d/%d/%d" % k: round(v, 4) for k, v in sorted(level.items())},
+        "plain_ms": {"%d/%d/%d/%d" % k: round(v, 4) for k, v in sorted(level.items())},
         "n_plain": n_plain,
     }
     if apply_result:
@@ -149,6 +168,10 @@ def apply(result: dict) -> None:
     for f in ("rfis_max", "rquick_max", "tile_log2", "oversample", "target"):
         if f in result:
             fields[f] = int(result[f])
+    if "extra_levels" in result:
+        fields["extra_levels"] = int(result["extra_levels"]) + 1
+    if "class_shape" in result:
+        fields["class_shape"] = SHAPE_ON | int(result["class_shape"])
     R.set_tuning(**fields)
 
 
@@ -173,7 +196,8 @@ def main() -> None:
     args = ap.parse_args()
     res = tune(args.key_type, quick=args.quick, apply_result=False)
     save(res, args.out)
-    print(json.dumps({k: res[k] for k in ("rfis_max", "rquick_max", "tile_log2", "oversample", "target")}))
+    print(json.dumps({k: res[k] for k in ("rfis_max", "rquick_max", "tile_log2", "oversample", "target",
+                                          "extra_levels", "class_shape")}))
 
 
 if __name__ == "__main__":

@@ -208,6 +208,8 @@ int rsort_get_tuning(rsort_tuning* out) {
   out->seed = t.seed;
   out->tile_log2 = t.tile_log2;
   out->force_fallback = t.force_fallback;
+  out->extra_levels = t.extra_levels + 1;
+  out->class_shape = t.class_shape | 0x80000000u;
   return RSORT_OK;
 }
 
@@ -235,6 +237,14 @@ int rsort_set_tuning(const rsort_tuning* in) {
     t.tile_log2 = in->tile_log2;
   }
   if (in->force_fallback) t.force_fallback = in->force_fallback == 1 ? 1u : 0u;
+  if (in->extra_levels) {
+    if (in->extra_levels > 5) return RSORT_EINVAL;
+    t.extra_levels = in->extra_levels - 1;
+  }
+  if (in->class_shape) {
+    if (!(in->class_shape & 0x80000000u)) return RSORT_EINVAL;
+    t.class_shape = in->class_shape & 0x1FFu;
+  }
   rs::tuning() = t;
   return RSORT_OK;
 }

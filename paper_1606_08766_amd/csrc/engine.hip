@@ -55,7 +55,9 @@ __device__ __forceinline__ uint32_t logk_for(uint32_t len, uint32_t target, uint
   const uint32_t q = (len + target - 1) / target;  // buckets wanted
   const uint32_t lq = q <= 1 ? 0u : 32u - __clz(q - 1);
   const uint32_t need = (lq + kMaxLogK - 1) / kMaxLogK;
-  const uint32_t lv = left < need ? left : (need ? need : 1u);
+  // levels to spread the 2^lq buckets over: the fewest that reach the
+  // target, or more when the plan has extra levels (at least 4 buckets each)
+  const uint32_t lv = left < need ? left : max(max(need, 1u), min(left, lq / 2));
   uint32_t lk = lv > 1 ? lq / lv : lq;
   lk = lk < 1u ? 1u : lk;
   return lk > (uint32_t)kMaxLogK ? (uint32_t)kMaxLogK : lk;
@@ -1039,6 +1041,10 @@ uint32_t plan_levels(uint64_t n, const Tuning& t, uint32_t cap) {
     L++;
   }
   L = std::max<uint32_t>(L, 1);
+  // extra levels, while every level still gets at least 4 buckets
+  uint32_t lq = 0;
+  for (uint64_t q = (n + effective_target(t, cap) - 1) / effective_target(t, cap); (1ull << lq) < q;) lq++;
+  for (uint32_t e = 0; e < t.extra_levels && 2 * (L + 1) <= lq; e++) L++;
   return std::min<uint32_t>(L, std::min<uint32_t>(t.max_levels, kMaxLevels));
 }
 

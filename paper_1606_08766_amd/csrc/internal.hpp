@@ -19,6 +19,8 @@ struct Tuning {
   uint64_t seed = 0x5EED5EED12345678ull;
   uint32_t tile_log2 = 13;  // scatter tile: 2^tile_log2 keys
   uint32_t force_fallback = 0;
+  uint32_t extra_levels = 0;  // sample-sort levels beyond the fewest needed
+  uint32_t class_shape = 0;   // bit c: class c uses its alternative workgroup shape
 };
 
 Tuning& tuning();

@@ -613,13 +613,16 @@ int launch_merge_class(int c, const Work& w, const K* kin, const uint32_t* pay_i
     constexpr int T = decltype(tag)::T, I = decltype(tag)::I;
     return merge_class_launch<K, F32, PAY, T, I>(c, w, kin, pay_in, kout, perm_out, pay_out, cap_c, st);
   };
+  // alternative shapes (tuning.class_shape): twice the threads, half the keys
+  // per thread, for the classes from 1024 to 8192 keys
+  const bool alt = (c & kDirect) == 0 && ((tuning().class_shape >> cb) & 1u);
   switch (cb) {
     case 0: return go(Shape<64, 1>{}, 16);
     case 1: return go(Shape<64, 4>{}, 16);
-    case 2: return go(Shape<256, 4>{}, 8);
-    case 3: return go(Shape<256, 8>{}, 8);
-    case 4: return go(Shape<384, 8>{}, 4);
-    case 5: return go(Shape<512, 8>{}, 3);
+    case 2: return alt ? go(Shape<512, 2>{}, 8) : go(Shape<256, 4>{}, 8);
+    case 3: return alt ? go(Shape<512, 4>{}, 8) : go(Shape<256, 8>{}, 8);
+    case 4: return alt ? go(Shape<768, 4>{}, 4) : go(Shape<384, 8>{}, 4);
+    case 5: return alt ? go(Shape<1024, 4>{}, 3) : go(Shape<512, 8>{}, 3);
     case 6: return go(Shape<768, 8>{}, 2);
     case 7: return go(Shape<1024, 8>{}, 1);
     case 8:

@@ -14,6 +14,11 @@ import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librsort.so")
+# Tuning measured by the autotuner (paper_1606_08766_amd/autotune.py) on an
+# MI355X, applied when the library is loaded.  RSORT_TUNING=<path> selects
+# another file, RSORT_TUNING=none keeps the compiled defaults.  Every tuning
+# yields the same output; only speed differs.
+DEFAULT_TUNING = os.path.join(_PKG, "tuning_mi355x.json")
 
 U32, U64, F32 = 0, 1, 2
 # Key types by tensor dtype.  Signed integer tensors are not mapped: their
@@ -46,6 +51,7 @@ class Tuning(ctypes.Structure):
         ("oversample", ctypes.c_uint32), ("target", ctypes.c_uint32), ("cap", ctypes.c_uint32),
         ("max_levels", ctypes.c_uint32), ("rfis_max", ctypes.c_uint32), ("rquick_max", ctypes.c_uint32),
         ("seed", ctypes.c_uint64), ("tile_log2", ctypes.c_uint32), ("force_fallback", ctypes.c_uint32),
+        ("extra_levels", ctypes.c_uint32), ("class_shape", ctypes.c_uint32),
     ]
 
 
@@ -129,6 +135,11 @@ def lib():
         L.rsort_rquick_mw.restype = i32
         L.rsort_rquick_mw.argtypes = [i32, vp, u64, u32, u32, i32, u64, vp, vp, vp, vp, sz, vp]
         _lib = L
+        path = os.environ.get("RSORT_TUNING", DEFAULT_TUNING)
+        if path != "none" and os.path.exists(path):
+            from paper_1606_08766_amd import autotune
+
+            autotune.load(path)
     return _lib
 
 
@@ -369,7 +380,8 @@ class tuned:
         s = self.saved
         set_tuning(oversample=s.oversample, target=s.target, cap=s.cap, max_levels=s.max_levels,
                    rfis_max=s.rfis_max, rquick_max=s.rquick_max, seed=s.seed, tile_log2=s.tile_log2,
-                   force_fallback=1 if s.force_fallback else 2)
+                   force_fallback=1 if s.force_fallback else 2, extra_levels=s.extra_levels,
+                   class_shape=s.class_shape)
 
 
 # ----------------------------------------------------------------------------- timing
