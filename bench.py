@@ -42,10 +42,10 @@ def src_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic():
+def load_traffic(name: str = "traffic.json"):
     """HBM traffic per kernel measured with rocprofv3 counters (committed under
     profiles/); ignored when the kernel sources changed since."""
-    p = os.path.join(ROOT, "profiles", "traffic.json")
+    p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
     with open(p) as f:
@@ -167,6 +167,18 @@ def bandwidth_ceilings(R, torch, nbytes: int = 2 << 30, reps: int = 5):
     return out
 
 
+def calib_copy(args, R, torch):
+    """One run of the library's copy probe over calib_copy_mib MiB (reads and
+    writes that many bytes), so that profiler byte counters can be scaled by
+    what they read for a copy of known size."""
+    cb = args.calib_copy_mib << 20
+    src = torch.ones(cb // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    R.bandwidth_probe("copy", src, dst, cb)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def bench_plain(args, R, torch):
     from gen import gen
 
@@ -183,15 +195,7 @@ def bench_plain(args, R, torch):
     po = torch.empty(n, dtype=torch.uint32, device="cuda")
     ws = torch.empty(R.plain_workspace_bytes(kt, n), dtype=torch.uint8, device="cuda")
     if args.calib_copy_mib:
-        # a plain device copy of known size, so that profiler byte counters
-        # can be scaled by what they read for it
-        # (an elementwise kernel: reads cb bytes and writes cb bytes)
-        cb = args.calib_copy_mib << 20
-        src = torch.ones(cb // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
+        calib_copy(args, R, torch)
     for s in range(args.warmup):
         R.sort(inputs[s % len(DISTS)], workspace=ws, out=(ko, po))
     torch.cuda.synchronize()
@@ -337,6 +341,8 @@ def bench_batched(args, R, torch):
     del keys, pay
     ko, po, plo = torch.empty_like(dk), torch.empty(n, dtype=torch.uint32, device="cuda"), torch.empty_like(dp)
     ws = torch.empty(R.segmented_workspace_bytes(R.U64, n, count, True), dtype=torch.uint8, device="cuda")
+    if args.calib_copy_mib:
+        calib_copy(args, R, torch)
     t_b = _timed(torch, lambda: R.segmented_sort(dk, do, dp, workspace=ws, out=(ko, po, plo)), args.steps, args.warmup)
     # per-pass figures from a separate, instrumented run
     R.timing_begin()
@@ -375,12 +381,19 @@ def bench_batched(args, R, torch):
     pass_bytes = {"count_l1": 8 * n_lv,                        # keys
                   "scatter_l1": (8 + 4 + 12 + 4) * n_lv,       # key + payload in; record + payload out
                   "local_sort": (8 + 4 + 16) * n_in + (12 + 4 + 16) * n_lv}  # in; key + payload + perm out
+    traffic = load_traffic("traffic_batched_1gib.json") if args.batched_variant == "1gib" else None
     passes = {}
     for c, ms in per.items():
         e = {"ms_per_call": ms}
         if c in pass_bytes and ms > 0 and pass_bytes[c]:
             gbs = pass_bytes[c] / (ms / 1e3) / 1e9
             e.update({"alg_bytes": pass_bytes[c], "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+            if traffic:
+                # measured HBM bytes per call of the pass's kernels (rocprofv3
+                # FETCH_SIZE + WRITE_SIZE) over its algorithmic bytes
+                meas = sum(traffic["kernels"][kernel_key(k)]["hbm_bytes_per_launch"] * timing[k][0] / calls
+                           for k in timing if kernel_class(k) == c and kernel_key(k) in traffic["kernels"])
+                e["traffic_ratio"] = round(meas / pass_bytes[c], 3) if meas else None
         passes[c] = e
     return {
         "metric": "Gkeys/s (batched segmented sort, %d segments)" % count,
@@ -669,18 +682,19 @@ def _read_pmc(path, counter):
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
-        k = kernel_key(r["Kernel_Name"]) if "rs::" in r["Kernel_Name"] else r["Kernel_Name"].split("(")[0]
+        k = kernel_key(r["Kernel_Name"]) if "rs::k_" in r["Kernel_Name"] else r["Kernel_Name"].split("(")[0]
         d = acc.setdefault(k, {})
         d[r["Dispatch_Id"]] = d.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
     return {k: (len(v), sum(v.values()) / len(v)) for k, v in acc.items()}
 
 
-def pmc_summary(fetch_csv, write_csv, copy_mib, command, out_dir):
+def pmc_summary(fetch_csv, write_csv, copy_mib, command, out_dir, name="hbm_traffic_plain_2p28_u64.txt",
+                json_name="traffic.json"):
     """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by what they read for a
     plain copy of copy_mib MiB and write profiles/traffic.json + a text table."""
     f = _read_pmc(fetch_csv, "FETCH_SIZE")
     w = _read_pmc(write_csv, "WRITE_SIZE")
-    copy = [k for k in f if "elementwise" in k.lower()]
+    copy = [k for k in f if "k_probe_copy" in k]
     if not copy:
         raise SystemExit("no copy kernel found for calibration")
     ck = max(copy, key=lambda k: f[k][1])
@@ -700,7 +714,7 @@ def pmc_summary(fetch_csv, write_csv, copy_mib, command, out_dir):
                            "write_kib": w.get(ck, (0, 0))[1], "fetch_scale": fr, "write_scale": fw},
            "kernels": kern}
     os.makedirs(out_dir, exist_ok=True)
-    with open(os.path.join(out_dir, "traffic.json"), "w") as fh:
+    with open(os.path.join(out_dir, json_name), "w") as fh:
         json.dump(res, fh, indent=1)
     lines = ["HBM traffic per kernel launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (two separate runs),",
              "scaled by the counters of a plain %d MiB device copy (%s): read x%.3f, write x%.3f." % (
@@ -711,7 +725,7 @@ def pmc_summary(fetch_csv, write_csv, copy_mib, command, out_dir):
         lines.append("%-28s %10d %14.2f %14.2f %14.2f" % (k, v["dispatches"], v["fetch_bytes_per_launch"] / 1e6,
                                                           v["write_bytes_per_launch"] / 1e6,
                                                           v["hbm_bytes_per_launch"] / 1e6))
-    with open(os.path.join(out_dir, "hbm_traffic_plain_2p28_u64.txt"), "w") as fh:
+    with open(os.path.join(out_dir, name), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -782,7 +796,8 @@ def main():
     ap.add_argument("--counter-table", nargs="+", metavar="COUNTER_CSV",
                     help="summarise rocprofv3 --pmc runs (any counters) into profiles/ (no GPU needed)")
     ap.add_argument("--profile-command", default="", help="command recorded in the summaries")
-    ap.add_argument("--profile-name", default="kernel_trace_plain_2p28_u64.txt")
+    ap.add_argument("--profile-name", default="")
+    ap.add_argument("--traffic-json", default="traffic.json", help="--pmc-summary: name of the JSON written")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=5)
@@ -804,14 +819,17 @@ def main():
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.calib_copy_mib or 1024, args.profile_command,
-                    os.path.join(ROOT, "profiles"))
+                    os.path.join(ROOT, "profiles"), args.profile_name or "hbm_traffic_plain_2p28_u64.txt",
+                    args.traffic_json)
         return
     if args.counter_table:
-        counter_table(args.counter_table, args.profile_command, os.path.join(ROOT, "profiles", args.profile_name),
+        counter_table(args.counter_table, args.profile_command,
+                      os.path.join(ROOT, "profiles", args.profile_name or "sq_counters_plain_2p28_u64.txt"),
                       "rocprofv3 --pmc counter summary")
         return
     if args.trace_summary:
-        trace_summary(args.trace_summary, args.profile_command, os.path.join(ROOT, "profiles", args.profile_name),
+        trace_summary(args.trace_summary, args.profile_command,
+                      os.path.join(ROOT, "profiles", args.profile_name or "kernel_trace_plain_2p28_u64.txt"),
                       "rocprofv3 --kernel-trace --stats summary")
         return
     if args.gpus != 1:
