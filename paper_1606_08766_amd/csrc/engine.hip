@@ -50,14 +50,16 @@ __device__ __forceinline__ uint32_t class_of(uint32_t len, uint32_t cap, uint32_
 // levels (this one included) to reach buckets of about `target` keys: the
 // 2^lq buckets needed are shared out over the levels the segment needs, the
 // upper levels taking the smaller share (fewer buckets where the data is
-// largest keeps the scatter's runs long).
-__device__ __forceinline__ uint32_t logk_for(uint32_t len, uint32_t target, uint32_t left) {
+// largest keeps the scatter's runs long).  Only a plan with extra levels
+// (`spread`) spreads them over more levels than the fewest that reach the
+// target, at least 4 buckets per level; otherwise a segment of a batch that
+// needs one level takes one, however many the batch's largest needs.
+__device__ __forceinline__ uint32_t logk_for(uint32_t len, uint32_t target, uint32_t left, uint32_t spread) {
   const uint32_t q = (len + target - 1) / target;  // buckets wanted
   const uint32_t lq = q <= 1 ? 0u : 32u - __clz(q - 1);
   const uint32_t need = (lq + kMaxLogK - 1) / kMaxLogK;
-  // levels to spread the 2^lq buckets over: the fewest that reach the
-  // target, or more when the plan has extra levels (at least 4 buckets each)
-  const uint32_t lv = left < need ? left : max(max(need, 1u), min(left, lq / 2));
+  const uint32_t fewest = max(need, 1u);
+  const uint32_t lv = left < need ? left : (spread ? max(fewest, min(left, lq / 2)) : fewest);
   uint32_t lk = lv > 1 ? lq / lv : lq;
   lk = lk < 1u ? 1u : lk;
   return lk > (uint32_t)kMaxLogK ? (uint32_t)kMaxLogK : lk;
@@ -124,7 +126,7 @@ __device__ __forceinline__ void route(const Work& w, RouteLds& L, uint32_t* big_
     const uint32_t i = L.base[dest] + li;
     if (to_big) {
       if (i < w.big_max)
-        big_list[i] = BigSeg{start, ubase, len, logk_for(len, target, left)};
+        big_list[i] = BigSeg{start, ubase, len, logk_for(len, target, left, w.spread)};
       else
         set_status(w.ctl, -3);  // capacity bound violated: internal error
     } else {
@@ -183,7 +185,7 @@ __global__ __launch_bounds__(64) void k_start_plain(Work w, uint64_t n, uint32_t
   if (threadIdx.x != 0 || n == 0) return;
   const uint32_t len = (uint32_t)n;
   if (len > cap && levels > 0) {
-    const uint32_t logk = logk_for(len, target, levels);
+    const uint32_t logk = logk_for(len, target, levels, w.spread);
     w.big[0][0] = BigSeg{0ull, 0ull, len, logk};
     const uint32_t ng = (uint32_t)((n + (1ull << w.group_log2) - 1) >> w.group_log2);
     w.group_base[0] = 0;
@@ -1130,6 +1132,7 @@ size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, 
     w->ids = levels >= 2 ? (uint8_t*)(base + o_ids) : nullptr;
     w->big_max = big_max;
     w->group_log2 = glog;
+    w->spread = t.extra_levels > 0 ? 1u : 0u;
     w->count_max = count_max;
     w->scan_blocks = scan_blocks;
     w->n = n;

@@ -79,6 +79,7 @@ struct Work {
   uint8_t* ids;          // [2 n] bucket of each element of a buffer level (see bucket ids below)
   uint64_t big_max, count_max, scan_blocks, n;
   uint32_t group_log2;   // log2 of the keys per tile group
+  uint32_t spread;       // 1: the plan has extra levels, and segments spread their buckets over them
 };
 
 // Bucket ids of a level that reads a buffer: the count pass stores the
