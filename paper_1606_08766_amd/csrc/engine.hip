@@ -67,6 +67,13 @@ __device__ __forceinline__ uint32_t logk_for(uint32_t len, uint32_t target, uint
 
 __device__ __forceinline__ void set_status(Ctl* ctl, int32_t code) { atomicCAS(&ctl->status, 0, code); }
 
+// A value the caller knows to be the same in every lane (read from LDS, say),
+// moved to a scalar register.
+__device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  return ((uint64_t)uniform((uint32_t)(x >> 32)) << 32) | uniform((uint32_t)x);
+}
+
 // The chained scan's per-chunk status words start at zero on every level.
 __device__ __forceinline__ void scan_flags_clear(const Work& w, uint32_t t, uint32_t nt) {
   for (uint64_t i = t; i < w.scan_blocks; i += nt) w.scan_flags[i] = 0ull;
@@ -424,39 +431,48 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
 }
 
 // ---------------------------------------------------------------------------
-// Classification of a thread's ITEMS elements with the splitter tree in LDS
-// (node t of the implicit tree at tk[t] / ti[t]).  Levels are the outer loop
-// so the ITEMS lookups of a level are independent.  The descent compares keys
-// only; an element whose key equals the key of a splitter on its path is
-// classified again comparing (key, position) pairs (the tie-break of
-// Appendix G: positions are looked at only when keys are equal).
+// Classification of a thread's ITEMS elements with the splitter tree in LDS.
+// tk holds 2k entries: node t of the implicit tree (t in [1, k)) at tk[t],
+// and below them a leaf row, tk[k + b] = the b-th smallest splitter key for
+// b < k - 1 and tk[2k - 1] = the largest (see tree_to_lds).  ti holds the
+// positions of the tree nodes.  Levels are the outer loop so the ITEMS
+// lookups of a level are independent.  The descent compares keys only and
+// walks byte offsets into tk (one shift-add per level, no index scaling).
+// It ends at the leaf k + b where b is the number of splitter keys strictly
+// below the key, so the key can only equal a splitter key on its path if it
+// equals that leaf's (the smallest splitter key >= key; the last leaf repeats
+// the largest splitter key, which a key in bucket k - 1 exceeds).  Such an
+// element is classified again comparing (key, position) pairs (the tie-break
+// of Appendix G: positions are looked at only when keys are equal).
 // Result: bucket = number of splitters strictly below (key, position).
 template <typename K, int ITEMS, typename IdxFn>
 __device__ __forceinline__ void classify_batch(const K* tk, const uint32_t* ti, uint32_t logk, const K (&key)[ITEMS],
                                                const bool (&valid)[ITEMS], IdxFn idx_of, uint32_t (&b)[ITEMS]) {
-  uint32_t j[ITEMS];
-  bool eq[ITEMS];
+  constexpr uint32_t KB = (uint32_t)sizeof(K);
+  const char* tb = reinterpret_cast<const char*>(tk);
+  uint32_t a[ITEMS];  // byte offset of the current node
 #pragma unroll
-  for (int i = 0; i < ITEMS; i++) j[i] = 1;
+  for (int i = 0; i < ITEMS; i++) a[i] = KB;
   for (uint32_t l = 0; l < logk; l++) {
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) j[i] = 2u * j[i] + (key[i] > tk[j[i]] ? 1u : 0u);
+    for (int i = 0; i < ITEMS; i++) {
+      const K t = *reinterpret_cast<const K*>(tb + a[i]);
+      a[i] = 2u * a[i] + (key[i] > t ? KB : 0u);
+    }
   }
-  // A key can only equal a splitter key on its path if it equals the splitter
-  // at the path's last left turn (the smallest splitter key >= key).  The
-  // direction bits of j are the bits below its leading one; the last left
-  // turn is its lowest zero bit z, at node j >> (z + 1).
+  K leaf[ITEMS];
 #pragma unroll
-  for (int i = 0; i < ITEMS; i++) {
-    const uint32_t z = (uint32_t)__builtin_ctz(~j[i]);
-    eq[i] = z < logk && key[i] == tk[j[i] >> (z + 1)];
-  }
+  for (int i = 0; i < ITEMS; i++) leaf[i] = *reinterpret_cast<const K*>(tb + a[i]);
+  bool eq[ITEMS];
   bool tie = false;
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) {
-    eq[i] = eq[i] & valid[i];
+    eq[i] = (key[i] == leaf[i]) & valid[i];
     tie = tie | eq[i];
   }
+  uint32_t j[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) j[i] = a[i] / KB;
   if (__any(tie)) {
     // positions of the tied elements first (independent loads), then a
     // level-major descent comparing (key, position)
@@ -479,6 +495,24 @@ __device__ __forceinline__ void classify_batch(const K* tk, const uint32_t* ti, 
   }
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) b[i] = j[i] - (1u << logk);
+}
+
+// Copies the splitter tree of segment s (2^logk buckets) from global memory
+// into tk[1, k) / ti[1, k) and fills tk's leaf row tk[k, 2k) (see
+// classify_batch): splitter j (1-based, in sorted order) is tree node
+// (j | k) >> (ctz(j) + 1).  Called by every thread; the caller synchronizes.
+template <typename K, int THREADS>
+__device__ __forceinline__ void tree_to_lds(const Work& w, uint32_t s, uint32_t logk, K* tk, uint32_t* ti) {
+  const K* tkey = (const K*)w.tree_key;
+  const uint32_t kk = 1u << logk;
+  const uint64_t o = (uint64_t)s * kMaxK;
+  for (uint32_t i = threadIdx.x + 1; i < kk; i += THREADS) {
+    tk[i] = tkey[o + i];
+    ti[i] = w.tree_idx[o + i];
+    const uint32_t node = (i | kk) >> (__builtin_ctz(i) + 1);
+    tk[kk + i - 1] = tkey[o + node];
+  }
+  if (threadIdx.x == 0 && kk > 1) tk[2 * kk - 1] = tkey[o + (((kk - 1) | kk) >> 1)];
 }
 
 __device__ __forceinline__ uint32_t find_seg(const uint32_t* base, uint32_t m, uint32_t tile) {
@@ -552,12 +586,7 @@ __device__ __forceinline__ void seg_for_group(const Work& w, int cur, uint32_t m
     sc.len = bs.len;
   }
   __syncthreads();
-  const K* tkey = (const K*)w.tree_key;
-  const uint32_t kk = 1u << sc.logk;
-  for (uint32_t i = threadIdx.x + 1; i < kk; i += THREADS) {
-    tk[i] = tkey[(uint64_t)sc.s * kMaxK + i];
-    ti[i] = w.tree_idx[(uint64_t)sc.s * kMaxK + i];
-  }
+  tree_to_lds<K, THREADS>(w, sc.s, sc.logk, tk, ti);
   __syncthreads();
 }
 
@@ -566,7 +595,7 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
   constexpr uint32_t TILE = THREADS * ITEMS;
   static_assert(TILE <= (1u << kGroupMinLog2), "tiles divide a group");
   const uint32_t GT = (1u << w.group_log2) / TILE;  // tiles per group
-  __shared__ K tk[kMaxK];
+  __shared__ K tk[2 * kMaxK];
   __shared__ uint32_t ti[kMaxK];
   __shared__ uint32_t hist[kMaxK];
   __shared__ SegCache sc;
@@ -585,36 +614,37 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
   GroupQueue gq(w.ctl->queue[0], G);
   for (uint32_t group = gq.next(&s_group); group < gq.hi; group = gq.next(&s_group)) {
     seg_for_group<K, THREADS>(w, cur, m, group, sc, tk, ti, false);
-    const uint32_t gl = group - sc.gb;
-    const uint32_t nt = (sc.len + TILE - 1) / TILE;
+    // the segment's fields are uniform: kept in scalar registers
+    const uint32_t gl = group - uniform(sc.gb);
+    const uint32_t slen = uniform(sc.len), slogk = uniform(sc.logk);
+    const uint64_t sstart = uniform64(sc.start);
+    const uint32_t nt = (slen + TILE - 1) / TILE;
     const uint32_t t_end = min(nt, (gl + 1) * GT);
     // the group's histogram accumulates over its tiles
     for (uint32_t tl = gl * GT; tl < t_end; tl++) {
-      const uint64_t base = sc.start + (uint64_t)tl * TILE;
-      const uint32_t cnt = min(TILE, sc.len - tl * TILE);
+      const uint64_t base = sstart + (uint64_t)tl * TILE;
+      const uint32_t cnt = min(TILE, slen - tl * TILE);
       K key[ITEMS];
       bool valid[ITEMS];
+      // every lane loads (lanes past the tile's end reload its last key), so
+      // the loads are issued back to back without branches
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         const uint32_t jj = i * THREADS + threadIdx.x;
         valid[i] = jj < cnt;
-        key[i] = K(0);
-        if (valid[i]) {
-          if constexpr (SRC_IN)
-            key[i] = in_keys[base + jj];
-          else
-            key[i] = bv.key(base + jj);
-        }
+        const uint32_t jc = min(jj, cnt - 1u);
+        if constexpr (SRC_IN)
+          key[i] = in_keys[base + jc];
+        else
+          key[i] = bv.key(base + jc);
       }
-      // f32 keys are mapped to their ordinals after all loads are issued (a
-      // map inside each guarded load would wait for that load first)
       if constexpr (SRC_IN && F32) {
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) key[i] = ord_of<K, F32>(key[i]);
       }
       uint32_t b[ITEMS];
       const uint64_t ub = sc.ubase;
-      classify_batch<K, ITEMS>(tk, ti, sc.logk, key, valid,
+      classify_batch<K, ITEMS>(tk, ti, slogk, key, valid,
                                [&](int i) -> uint32_t {
                                  const uint64_t pos = base + i * THREADS + threadIdx.x;
                                  if constexpr (SRC_IN)
@@ -626,17 +656,17 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
       if constexpr (!SRC_IN) {
 #pragma unroll
         for (int i = 0; i < ITEMS; i++)
-          if (valid[i]) put_bucket_id(w.ids, sc.start, (uint64_t)tl * TILE + i * THREADS + threadIdx.x, sc.logk, b[i]);
+          if (valid[i]) put_bucket_id(w.ids, sstart, (uint64_t)tl * TILE + i * THREADS + threadIdx.x, slogk, b[i]);
       }
+      // One atomic per wave when all its elements fall into one bucket
+      // (skewed inputs).  A wave's valid elements are a prefix of its lanes,
+      // so lane 0 holds one whenever any lane does.
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
-        // one atomic per wave when the whole wave falls into one bucket
-        const uint64_t act = __ballot(valid[i]);
-        const uint32_t b0 = (uint32_t)__shfl(b[i], __ffsll((unsigned long long)act) - 1, kWave);
-        const uint64_t same = __ballot(valid[i] && b[i] == b0);
-        if (act && same == act) {
-          if (lane == (uint32_t)(__ffsll((unsigned long long)act) - 1))
-            atomicAdd(&hist[b0], (uint32_t)__popcll(act));
+        const uint32_t b0 = uniform(b[i]);
+        if (__ballot(valid[i] && b[i] != b0) == 0) {
+          const uint32_t nv = (uint32_t)__popcll(__ballot(valid[i]));
+          if (lane == 0 && nv) atomicAdd(&hist[b0], nv);
         } else if (valid[i]) {
           atomicAdd(&hist[b[i]], 1u);
         }
@@ -820,7 +850,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
   const uint32_t GT = (1u << w.group_log2) / TILE;  // tiles per group
   static_assert(THREADS >= kMaxK, "one histogram bin per thread");
   static_assert(TILE <= (1u << 23), "ranks fit 23 bits");
-  __shared__ K tk[kMaxK];
+  __shared__ K tk[2 * kMaxK];
   __shared__ uint32_t ti[kMaxK];
   __shared__ uint32_t hist[kMaxK];
   __shared__ uint64_t gdelta[kMaxK];
@@ -904,19 +934,18 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
       if constexpr (SRC_IN)
         classify_batch<K, ITEMS>(tk, ti, bs.logk, key, valid, [&](int i) -> uint32_t { return idx[i]; }, b);
       // rank inside (tile, bucket): one LDS atomic per element, or one per wave
-      // when the whole wave falls into a single bucket (skewed inputs)
+      // when the whole wave falls into a single bucket (skewed inputs).  A
+      // wave's valid elements are a prefix of its lanes, so lane 0 holds one
+      // whenever any lane does.
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
-        const uint64_t act = __ballot(valid[i]);
-        const uint32_t b0 = (uint32_t)__shfl(b[i], __ffsll((unsigned long long)act) - 1, kWave);
-        const uint64_t same = __ballot(valid[i] && b[i] == b0);
+        const uint32_t b0 = uniform(b[i]);
         uint32_t r = 0;
-        if (act && same == act) {
-          const int leader = __ffsll((unsigned long long)act) - 1;
+        if (__ballot(valid[i] && b[i] != b0) == 0) {
+          const uint64_t act = __ballot(valid[i]);
           uint32_t basev = 0;
-          if (lane == (uint32_t)leader) basev = atomicAdd(&hist[b0], (uint32_t)__popcll(act));
-          basev = __shfl(basev, leader, kWave);
-          r = basev + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
+          if (lane == 0 && act) basev = atomicAdd(&hist[b0], (uint32_t)__popcll(act));
+          r = uniform(basev) + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
         } else if (valid[i]) {
           r = atomicAdd(&hist[b[i]], 1u);
         }
