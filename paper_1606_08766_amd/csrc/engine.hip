@@ -620,6 +620,12 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
     const uint64_t sstart = uniform64(sc.start);
     const uint32_t nt = (slen + TILE - 1) / TILE;
     const uint32_t t_end = min(nt, (gl + 1) * GT);
+    // place of a thread's item i in a tile: striped over the block, or (a
+    // level that reads a buffer) striped over the thread's wave
+    const uint32_t wbase = (threadIdx.x & ~(uint32_t)(kWave - 1)) * ITEMS, wl = threadIdx.x & (kWave - 1);
+    auto place = [&](int i) -> uint32_t {
+      return SRC_IN ? i * THREADS + threadIdx.x : wbase + i * kWave + wl;
+    };
     // the group's histogram accumulates over its tiles
     for (uint32_t tl = gl * GT; tl < t_end; tl++) {
       const uint64_t base = sstart + (uint64_t)tl * TILE;
@@ -627,10 +633,12 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
       K key[ITEMS];
       bool valid[ITEMS];
       // every lane loads (lanes past the tile's end reload its last key), so
-      // the loads are issued back to back without branches
+      // the loads are issued back to back without branches.  A level that
+      // reads a buffer gives each wave ITEMS * 64 consecutive elements, so
+      // that its byte ids form one contiguous run.
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
-        const uint32_t jj = i * THREADS + threadIdx.x;
+        const uint32_t jj = place(i);
         valid[i] = jj < cnt;
         const uint32_t jc = min(jj, cnt - 1u);
         if constexpr (SRC_IN)
@@ -646,7 +654,7 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
       const uint64_t ub = sc.ubase;
       classify_batch<K, ITEMS>(tk, ti, slogk, key, valid,
                                [&](int i) -> uint32_t {
-                                 const uint64_t pos = base + i * THREADS + threadIdx.x;
+                                 const uint64_t pos = base + place(i);
                                  if constexpr (SRC_IN)
                                    return (uint32_t)(pos - ub);
                                  else
@@ -656,7 +664,7 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
       if constexpr (!SRC_IN) {
 #pragma unroll
         for (int i = 0; i < ITEMS; i++)
-          if (valid[i]) put_bucket_id(w.ids, sstart, (uint64_t)tl * TILE + i * THREADS + threadIdx.x, slogk, b[i]);
+          if (valid[i]) put_bucket_id(w.ids, sstart, (uint64_t)tl * TILE + place(i), slogk, b[i]);
       }
       // One atomic per wave when all its elements fall into one bucket
       // (skewed inputs).  A wave's valid elements are a prefix of its lanes,
