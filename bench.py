@@ -811,8 +811,9 @@ def main():
     ap.add_argument("--small-algo", default="", choices=["", "rfis", "rquick", "merge"],
                     help="small workload: only this algorithm")
     ap.add_argument("--requests", type=int, default=2000)
-    ap.add_argument("--serve-slots", type=int, default=4,
-                    help="server streams (the GPU exposes 4 hardware queues per process by default)")
+    ap.add_argument("--serve-slots", type=int, default=8,
+                    help="server slots, one stream each (the process has 4 hardware queues by default; more slots "
+                         "than queues keep each queue fed when a request ends)")
     ap.add_argument("--no-extras", action="store_true",
                     help="plain workload only: skip the ceilings and the other configurations")
     ap.add_argument("--serve-warmup", type=int, default=200)
