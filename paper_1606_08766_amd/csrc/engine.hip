@@ -848,6 +848,29 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(Work w) {
   }
 }
 
+// Exclusive scan of a tile histogram: one value per thread, non-zero only
+// in the first kMaxK threads (the bins).  Rows of 16 lanes are scanned with
+// DPP row shifts, rows are joined through lane reads, and the at most
+// kMaxK / 64 bin waves through LDS (tmp: kMaxK / 64 words), with one
+// barrier.  Called by every thread of the block.
+__device__ __forceinline__ uint32_t bins_excl_scan(uint32_t v, uint32_t* tmp) {
+  constexpr uint32_t NW = kMaxK / kWave;
+  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  uint32_t inc = v;
+  inc += dpp_u32<0x111>(inc);  // row_shr:1 (lanes without a source add 0)
+  inc += dpp_u32<0x112>(inc);  // row_shr:2
+  inc += dpp_u32<0x114>(inc);  // row_shr:4
+  inc += dpp_u32<0x118>(inc);  // row_shr:8
+  const uint32_t r0 = lane_u32(inc, 15), r1 = lane_u32(inc, 31), r2 = lane_u32(inc, 47);
+  const uint32_t row = lane >> 4;
+  inc += (row > 0 ? r0 : 0u) + (row > 1 ? r1 : 0u) + (row > 2 ? r2 : 0u);
+  if (w < NW && lane == kWave - 1) tmp[w] = inc;
+  __syncthreads();
+  uint32_t off = 0;
+  for (uint32_t q = 0; q < w && q < NW; q++) off += tmp[q];
+  return off + inc - v;
+}
+
 // ---------------------------------------------------------------------------
 // Scatter: classify, rank inside (tile, bucket), stage by bucket in LDS and
 // write each bucket's run contiguously to the destination buffer.
@@ -963,7 +986,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
       // exclusive scan of the tile histogram -> tile-local bucket starts
       {
         const uint32_t hv = threadIdx.x < kk ? hist[threadIdx.x] : 0u;
-        const uint32_t e = block_excl_scan<THREADS>(hv, tmp, nullptr);
+        const uint32_t e = bins_excl_scan(hv, tmp);
         if (threadIdx.x < kk) {
           hist[threadIdx.x] = e;
           gdelta[threadIdx.x] = run_off - e;
@@ -971,11 +994,16 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
         }
       }
       __syncthreads();
+      // every item's bucket start is read before any is used (an element
+      // past the tile's end reads bin 511, inside hist, and is not staged)
+      uint32_t hb[ITEMS];
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) hb[i] = hist[pos[i] >> 23];
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         if (pos[i] != 0xFFFFFFFFu) {
           const uint32_t bb = pos[i] >> 23;
-          const uint32_t p = hist[bb] + (pos[i] & 0x7FFFFFu);
+          const uint32_t p = hb[i] + (pos[i] & 0x7FFFFFu);
           pos[i] = p;
           stage[p] = key[i];
           stage32[p] = idx[i];
@@ -992,9 +1020,28 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
         if constexpr (PAY) asm volatile("" ::"v"(npay[i]));
         if constexpr (!SRC_IN) asm volatile("" ::"v"(nb[i]));
       }
-      for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) {
-        const uint64_t g = gdelta[stage_b[p]] + p;
-        dv.put(g, stage[p], stage32[p]);
+      if (cnt == TILE) {
+        // a full tile: all staged reads, then all run offsets, then the
+        // stores, so that no thread waits on one LDS round trip per element
+        uint32_t sb[ITEMS], si[ITEMS];
+        K sk[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+          const uint32_t p = i * THREADS + threadIdx.x;
+          sb[i] = stage_b[p];
+          sk[i] = stage[p];
+          si[i] = stage32[p];
+        }
+        uint64_t gd[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) gd[i] = gdelta[sb[i]];
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) dv.put(gd[i] + i * THREADS + threadIdx.x, sk[i], si[i]);
+      } else {
+        for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) {
+          const uint64_t g = gdelta[stage_b[p]] + p;
+          dv.put(g, stage[p], stage32[p]);
+        }
       }
       if constexpr (PAY) {
         __syncthreads();
