@@ -1148,6 +1148,20 @@ static uint32_t group_log2_for(uint64_t n) {
   return lg;
 }
 
+// Tile groups of the levels after the first of a plain sort hold at most
+// 2^kGroupUpLog2 keys.  Such a level splits k segments of about n / k keys
+// each, and with small groups the workgroups of an XCD, which take
+// consecutive groups, work on neighbouring tiles of one segment at once, so
+// their runs of each bucket land next to each other in HBM.  A new group
+// costs a drain of the tile prefetch and a strided read of its bucket
+// offsets: the first level (one segment, whose skewed inputs already write
+// long runs) and segmented sorts (mostly short segments, so neighbouring
+// groups seldom share one) do not recover that and keep the larger groups.
+constexpr uint32_t kGroupUpLog2 = 14;
+static uint32_t group_log2_level(uint32_t glog0, uint32_t lev, bool segmented) {
+  return (lev == 0 || segmented) ? glog0 : std::min<uint32_t>(glog0, kGroupUpLog2);
+}
+
 // Workspace layout: returns total bytes; fills w (pointers relative to base).
 size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, char* base, Work* w,
               uint32_t* levels_out) {
@@ -1156,7 +1170,7 @@ size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, 
   const uint32_t levels = plan_levels(n, t, cap);
   const uint64_t big_max = levels ? n / (cap + 1) + 1 : 0;
   const uint32_t glog = group_log2_for(n);
-  const uint64_t groups_max = levels ? (n >> glog) + big_max + 1 : 0;
+  const uint64_t groups_max = levels ? (n >> std::min<uint32_t>(glog, kGroupUpLog2)) + big_max + 1 : 0;
   const uint64_t count_max = groups_max * kMaxK;
   const uint64_t scan_blocks = count_max / kScanChunk + 2;
   const uint64_t final_max = (uint64_t)num_segs + (uint64_t)levels * kMaxK * big_max + 1;
@@ -1301,10 +1315,13 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
               ff, cmin);
   }
 
-  // scatter tiles are at most a tile group
-  const uint32_t tile_log2 = (t.tile_log2 == 12 || w.group_log2 < 13) ? 12 : 13;
-  const uint64_t groups_max = (n >> w.group_log2) + w.big_max + 1;
+  const Work w0 = w;
   for (uint32_t lev = 0; lev < levels; lev++) {
+    // the level's tile groups; scatter tiles are at most a tile group
+    Work w = w0;
+    w.group_log2 = group_log2_level(w0.group_log2, lev, seg_off != nullptr);
+    const uint32_t tile_log2 = (t.tile_log2 == 12 || w.group_log2 < 13) ? 12 : 13;
+    const uint64_t groups_max = (n >> w.group_log2) + w.big_max + 1;
     const int dst = lev & 1;
     const int src = (lev + 1) & 1;  // buffer written by the previous level
     const bool last = lev + 1 == levels;
