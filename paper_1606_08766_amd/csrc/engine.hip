@@ -443,43 +443,23 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
 // equals that leaf's (the smallest splitter key >= key; the last leaf repeats
 // the largest splitter key, which a key in bucket k - 1 exceeds).  Such an
 // element is classified again comparing (key, position) pairs (the tie-break
-// of Appendix G: positions are looked at only when keys are equal).
+// of Appendix G: positions are looked at only when keys are equal).  `pairs`
+// (uniform over the wave, kept by the caller across tiles) skips the key-only
+// descent for a tile after one in which every element of the wave tied, as
+// on inputs of few distinct keys.
 // Result: bucket = number of splitters strictly below (key, position).
 template <typename K, int ITEMS, typename IdxFn>
 __device__ __forceinline__ void classify_batch(const K* tk, const uint32_t* ti, uint32_t logk, const K (&key)[ITEMS],
-                                               const bool (&valid)[ITEMS], IdxFn idx_of, uint32_t (&b)[ITEMS]) {
+                                               const bool (&valid)[ITEMS], IdxFn idx_of, uint32_t (&b)[ITEMS],
+                                               bool& pairs) {
   constexpr uint32_t KB = (uint32_t)sizeof(K);
-  const char* tb = reinterpret_cast<const char*>(tk);
-  uint32_t a[ITEMS];  // byte offset of the current node
-#pragma unroll
-  for (int i = 0; i < ITEMS; i++) a[i] = KB;
-  for (uint32_t l = 0; l < logk; l++) {
-#pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const K t = *reinterpret_cast<const K*>(tb + a[i]);
-      a[i] = 2u * a[i] + (key[i] > t ? KB : 0u);
-    }
-  }
-  K leaf[ITEMS];
-#pragma unroll
-  for (int i = 0; i < ITEMS; i++) leaf[i] = *reinterpret_cast<const K*>(tb + a[i]);
-  bool eq[ITEMS];
-  bool tie = false;
-#pragma unroll
-  for (int i = 0; i < ITEMS; i++) {
-    eq[i] = (key[i] == leaf[i]) & valid[i];
-    tie = tie | eq[i];
-  }
-  uint32_t j[ITEMS];
-#pragma unroll
-  for (int i = 0; i < ITEMS; i++) j[i] = a[i] / KB;
-  if (__any(tie)) {
-    // positions of the tied elements first (independent loads), then a
-    // level-major descent comparing (key, position)
-    uint32_t id[ITEMS], q[ITEMS];
+  const uint32_t kk = 1u << logk;
+  // level-major descent comparing (key, position) for the elements in m
+  auto pair_descent = [&](const bool (&m)[ITEMS], uint32_t (&q)[ITEMS]) {
+    uint32_t id[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
-      id[i] = eq[i] ? idx_of(i) : 0u;
+      id[i] = m[i] ? idx_of(i) : 0u;  // positions first (independent loads)
       q[i] = 1;
     }
     for (uint32_t l = 0; l < logk; l++) {
@@ -490,11 +470,55 @@ __device__ __forceinline__ void classify_batch(const K* tk, const uint32_t* ti, 
         q[i] = 2u * q[i] + ((key[i] > t) | ((key[i] == t) & (id[i] > u)) ? 1u : 0u);
       }
     }
+  };
+  uint32_t j[ITEMS];
+  if (pairs) {  // uniform
+    // every element of this wave's previous tile tied: the (key, position)
+    // descent alone gives the bucket.  A splitter key equals the key exactly
+    // when one of the two splitters around the result does (the leaf row
+    // holds them), which decides the mode of the next tile.
+    pair_descent(valid, j);
+    bool untied = false;
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) j[i] = eq[i] ? q[i] : j[i];
+    for (int i = 0; i < ITEMS; i++) {
+      const bool t = key[i] == tk[j[i]] || (j[i] > kk && key[i] == tk[j[i] - 1]);
+      untied = untied | (valid[i] & !t);
+    }
+    pairs = !__any(untied);
+  } else {
+    const char* tb = reinterpret_cast<const char*>(tk);
+    uint32_t a[ITEMS];  // byte offset of the current node
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) a[i] = KB;
+    for (uint32_t l = 0; l < logk; l++) {
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        const K t = *reinterpret_cast<const K*>(tb + a[i]);
+        a[i] = 2u * a[i] + (key[i] > t ? KB : 0u);
+      }
+    }
+    K leaf[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) leaf[i] = *reinterpret_cast<const K*>(tb + a[i]);
+    bool eq[ITEMS];
+    bool tie = false, untied = false;
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      eq[i] = (key[i] == leaf[i]) & valid[i];
+      tie = tie | eq[i];
+      untied = untied | (valid[i] & !eq[i]);
+      j[i] = a[i] / KB;
+    }
+    if (__any(tie)) {
+      uint32_t q[ITEMS];
+      pair_descent(eq, q);
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) j[i] = eq[i] ? q[i] : j[i];
+    }
+    pairs = !__any(untied);
   }
 #pragma unroll
-  for (int i = 0; i < ITEMS; i++) b[i] = j[i] - (1u << logk);
+  for (int i = 0; i < ITEMS; i++) b[i] = j[i] - kk;
 }
 
 // Copies the splitter tree of segment s (2^logk buckets) from global memory
@@ -612,6 +636,7 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
   __syncthreads();
   __shared__ uint32_t s_group;
   GroupQueue gq(w.ctl->queue[0], G);
+  bool pairs = false;  // classification mode of this wave's next tile
   for (uint32_t group = gq.next(&s_group); group < gq.hi; group = gq.next(&s_group)) {
     seg_for_group<K, THREADS>(w, cur, m, group, sc, tk, ti, false);
     // the segment's fields are uniform: kept in scalar registers
@@ -660,7 +685,7 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
                                  else
                                    return bv.idx(pos);
                                },
-                               b);
+                               b, pairs);
       if constexpr (!SRC_IN) {
 #pragma unroll
         for (int i = 0; i < ITEMS; i++)
@@ -908,6 +933,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
 
   __shared__ uint32_t s_group;
   GroupQueue gq(w.ctl->queue[1], G);
+  bool pairs = false;  // classification mode of this wave's next tile
   for (uint32_t group = gq.next(&s_group); group < gq.hi; group = gq.next(&s_group)) {
     seg_for_group<K, THREADS>(w, cur, m, group, sc, tk, ti, true);
     const uint32_t gl = group - sc.gb;
@@ -947,7 +973,6 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
     };
     if (gl * GT < t_end) load_tile(gl * GT);
     for (uint32_t tl = gl * GT; tl < t_end; tl++) {
-      const uint64_t base = bs.start + (uint64_t)tl * TILE;
       const uint32_t cnt = min(TILE, bs.len - tl * TILE);
       K key[ITEMS];
       uint32_t idx[ITEMS], pay[ITEMS], pos[ITEMS], b[ITEMS];
@@ -963,7 +988,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
       if (tl + 1 < t_end) load_tile(tl + 1);
       // the first level classifies; later ones read the count pass's ids
       if constexpr (SRC_IN)
-        classify_batch<K, ITEMS>(tk, ti, bs.logk, key, valid, [&](int i) -> uint32_t { return idx[i]; }, b);
+        classify_batch<K, ITEMS>(tk, ti, bs.logk, key, valid, [&](int i) -> uint32_t { return idx[i]; }, b, pairs);
       // rank inside (tile, bucket): one LDS atomic per element, or one per wave
       // when the whole wave falls into a single bucket (skewed inputs).  A
       // wave's valid elements are a prefix of its lanes, so lane 0 holds one
