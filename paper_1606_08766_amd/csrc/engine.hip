@@ -211,18 +211,33 @@ __global__ __launch_bounds__(64) void k_start_plain(Work w, uint64_t n, uint32_t
 }
 
 // Per level: tile groups and count-matrix bases of the segments to split.
+// glog_small (levels after the first of a plain sort; 0 otherwise): when the
+// first level's scatter wrote runs of fewer than kShortRun keys on average
+// (keys spread over all buckets of every tile), this level's groups hold
+// 2^glog_small keys instead of 2^group_log2, and the count and scatter passes
+// read the choice from ctl->glog.
 constexpr int kPlanThreads = 1024;
-__global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev) {
+constexpr uint32_t kShortRun = 128;
+__global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev, uint32_t glog_small) {
   __shared__ uint32_t tmp[kPlanThreads / kWave + 1];
+  __shared__ uint32_t s_glog;
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
   const BigSeg* B = w.big[cur];
+  if (threadIdx.x == 0) {
+    const uint32_t runs = w.ctl->runs;
+    const bool short_runs = glog_small && runs && w.n / runs < kShortRun;
+    s_glog = short_runs ? glog_small : w.group_log2;
+    if (glog_small) w.ctl->glog = s_glog;
+  }
+  __syncthreads();
+  const uint32_t glog = s_glog;
   uint32_t ct = 0, cc = 0;
   for (uint32_t base = 0; base < m; base += kPlanThreads) {
     const uint32_t i = base + threadIdx.x;
     uint32_t nt = 0, nc = 0;
     if (i < m) {
-      nt = (uint32_t)(((uint64_t)B[i].len + (1u << w.group_log2) - 1) >> w.group_log2);  // groups
+      nt = (uint32_t)(((uint64_t)B[i].len + (1u << glog) - 1) >> glog);  // groups
       nc = nt << B[i].logk;
     }
     uint32_t tt, tc;
@@ -581,6 +596,13 @@ struct GroupQueue {
   }
 };
 
+// Keys per tile group (log2) of level lev: as the host planned it, unless the
+// level's plan chose smaller groups (k_plan).
+__device__ __forceinline__ uint32_t group_log2_of(const Work& w, int lev) {
+  const uint32_t g = w.ctl->glog;
+  return (lev > 0 && g) ? g : w.group_log2;
+}
+
 // Segment a tile group belongs to, cached in LDS by the group loops below.
 struct SegCache {
   uint32_t s, gb, gb_end, cb, seg0, logk;
@@ -618,7 +640,7 @@ template <typename K, bool F32, bool SRC_IN, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_keys, int src_buf) {
   constexpr uint32_t TILE = THREADS * ITEMS;
   static_assert(TILE <= (1u << kGroupMinLog2), "tiles divide a group");
-  const uint32_t GT = (1u << w.group_log2) / TILE;  // tiles per group
+  const uint32_t GT = (1u << group_log2_of(w, lev)) / TILE;  // tiles per group
   __shared__ K tk[2 * kMaxK];
   __shared__ uint32_t ti[kMaxK];
   __shared__ uint32_t hist[kMaxK];
@@ -903,7 +925,7 @@ template <typename K, bool F32, bool SRC_IN, bool PAY, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* in_keys, const uint32_t* in_pay,
                                                      int src_buf, int dst_buf) {
   constexpr uint32_t TILE = THREADS * ITEMS;  // the host launches tiles no larger than a group
-  const uint32_t GT = (1u << w.group_log2) / TILE;  // tiles per group
+  const uint32_t GT = (1u << group_log2_of(w, lev)) / TILE;  // tiles per group
   static_assert(THREADS >= kMaxK, "one histogram bin per thread");
   static_assert(TILE <= (1u << 23), "ranks fit 23 bits");
   __shared__ K tk[2 * kMaxK];
@@ -934,6 +956,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
   __shared__ uint32_t s_group;
   GroupQueue gq(w.ctl->queue[1], G);
   bool pairs = false;  // classification mode of this wave's next tile
+  uint32_t runs = 0;   // runs this thread's bucket got, summed once at the end
   for (uint32_t group = gq.next(&s_group); group < gq.hi; group = gq.next(&s_group)) {
     seg_for_group<K, THREADS>(w, cur, m, group, sc, tk, ti, true);
     const uint32_t gl = group - sc.gb;
@@ -1011,6 +1034,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
       // exclusive scan of the tile histogram -> tile-local bucket starts
       {
         const uint32_t hv = threadIdx.x < kk ? hist[threadIdx.x] : 0u;
+        runs += hv != 0u ? 1u : 0u;  // one run per non-empty bucket of a tile
         const uint32_t e = bins_excl_scan(hv, tmp);
         if (threadIdx.x < kk) {
           hist[threadIdx.x] = e;
@@ -1078,6 +1102,10 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
       }
       __syncthreads();
     }
+  }
+  if (lev == 0) {  // the first level's run count (read by the next level's plan)
+    for (int d = kWave / 2; d > 0; d >>= 1) runs += (uint32_t)__shfl_xor((int)runs, d, kWave);
+    if (lane == 0 && runs) atomicAdd(&w.ctl->runs, runs);
   }
 }
 
@@ -1174,17 +1202,22 @@ static uint32_t group_log2_for(uint64_t n) {
 }
 
 // Tile groups of the levels after the first of a plain sort hold at most
-// 2^kGroupUpLog2 keys.  Such a level splits k segments of about n / k keys
-// each, and with small groups the workgroups of an XCD, which take
-// consecutive groups, work on neighbouring tiles of one segment at once, so
-// their runs of each bucket land next to each other in HBM.  A new group
-// costs a drain of the tile prefetch and a strided read of its bucket
-// offsets: the first level (one segment, whose skewed inputs already write
-// long runs) and segmented sorts (mostly short segments, so neighbouring
-// groups seldom share one) do not recover that and keep the larger groups.
-constexpr uint32_t kGroupUpLog2 = 14;
+// 2^kGroupUpLog2 keys, or 2^kGroupSmallLog2 when the first level's runs were
+// short (chosen on the device, k_plan).  Such a level splits k segments of
+// about n / k keys each, and with small groups the workgroups of an XCD,
+// which take consecutive groups, work on neighbouring tiles of one segment
+// at once, so their runs of each bucket land next to each other in HBM.  A
+// new group costs a drain of the tile prefetch and a strided read of its
+// bucket offsets: the first level (one segment, whose skewed inputs already
+// write long runs) and segmented sorts (mostly short segments, so
+// neighbouring groups seldom share one) do not recover that and keep the
+// larger groups, and inputs whose runs are long already keep 2^kGroupUpLog2.
+constexpr uint32_t kGroupUpLog2 = 14, kGroupSmallLog2 = 13;
 static uint32_t group_log2_level(uint32_t glog0, uint32_t lev, bool segmented) {
   return (lev == 0 || segmented) ? glog0 : std::min<uint32_t>(glog0, kGroupUpLog2);
+}
+static uint32_t group_log2_small(uint32_t glog0, uint32_t lev, bool segmented) {
+  return (lev == 0 || segmented) ? 0u : std::min<uint32_t>(glog0, kGroupSmallLog2);
 }
 
 // Workspace layout: returns total bytes; fills w (pointers relative to base).
@@ -1195,7 +1228,7 @@ size_t layout(int kt, uint64_t n, uint32_t num_segs, bool pay, const Tuning& t, 
   const uint32_t levels = plan_levels(n, t, cap);
   const uint64_t big_max = levels ? n / (cap + 1) + 1 : 0;
   const uint32_t glog = group_log2_for(n);
-  const uint64_t groups_max = levels ? (n >> std::min<uint32_t>(glog, kGroupUpLog2)) + big_max + 1 : 0;
+  const uint64_t groups_max = levels ? (n >> std::min<uint32_t>(glog, kGroupSmallLog2)) + big_max + 1 : 0;
   const uint64_t count_max = groups_max * kMaxK;
   const uint64_t scan_blocks = count_max / kScanChunk + 2;
   const uint64_t final_max = (uint64_t)num_segs + (uint64_t)levels * kMaxK * big_max + 1;
@@ -1345,12 +1378,13 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
     // the level's tile groups; scatter tiles are at most a tile group
     Work w = w0;
     w.group_log2 = group_log2_level(w0.group_log2, lev, seg_off != nullptr);
-    const uint32_t tile_log2 = (t.tile_log2 == 12 || w.group_log2 < 13) ? 12 : 13;
-    const uint64_t groups_max = (n >> w.group_log2) + w.big_max + 1;
+    const uint32_t glog_small = group_log2_small(w0.group_log2, lev, seg_off != nullptr);
+    const uint32_t tile_log2 = (t.tile_log2 == 12 || std::min(w.group_log2, glog_small ? glog_small : 99u) < 13) ? 12 : 13;
+    const uint64_t groups_max = (n >> (glog_small ? glog_small : w.group_log2)) + w.big_max + 1;
     const int dst = lev & 1;
     const int src = (lev + 1) & 1;  // buffer written by the previous level
     const bool last = lev + 1 == levels;
-    if (lev > 0 || seg_off) RS_LAUNCH(k_plan, 1, kPlanThreads, st, w, (int)lev);  // level 0 of a plain sort: planned at the start
+    if (lev > 0 || seg_off) RS_LAUNCH(k_plan, 1, kPlanThreads, st, w, (int)lev, glog_small);  // level 0 of a plain sort: planned at the start
     const uint32_t gs = grid_for(w.big_max, 4);
     if (lev == 0) {
       // a single-level sort of few buckets (cmin > 0) is latency-bound on its
