@@ -599,8 +599,9 @@ struct GroupQueue {
 // Keys per tile group (log2) of level lev: as the host planned it, unless the
 // level's plan chose smaller groups (k_plan).
 __device__ __forceinline__ uint32_t group_log2_of(const Work& w, int lev) {
+  if (lev == 0) return w.group_log2;  // (no load on the first level)
   const uint32_t g = w.ctl->glog;
-  return (lev > 0 && g) ? g : w.group_log2;
+  return g ? g : w.group_log2;
 }
 
 // Segment a tile group belongs to, cached in LDS by the group loops below.
@@ -923,7 +924,7 @@ __device__ __forceinline__ uint32_t bins_excl_scan(uint32_t v, uint32_t* tmp) {
 // write each bucket's run contiguously to the destination buffer.
 template <typename K, bool F32, bool SRC_IN, bool PAY, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* in_keys, const uint32_t* in_pay,
-                                                     int src_buf, int dst_buf) {
+                                                     int src_buf, int dst_buf, int count_runs) {
   constexpr uint32_t TILE = THREADS * ITEMS;  // the host launches tiles no larger than a group
   const uint32_t GT = (1u << group_log2_of(w, lev)) / TILE;  // tiles per group
   static_assert(THREADS >= kMaxK, "one histogram bin per thread");
@@ -1103,9 +1104,16 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
       __syncthreads();
     }
   }
-  if (lev == 0) {  // the first level's run count (read by the next level's plan)
+  // the first level's run count, read by the next level's plan (a kernel
+  // argument: a load here would wait for the write-out stores first)
+  if (count_runs) {
+    __shared__ uint32_t s_runs;
+    if (threadIdx.x == 0) s_runs = 0;
+    __syncthreads();
     for (int d = kWave / 2; d > 0; d >>= 1) runs += (uint32_t)__shfl_xor((int)runs, d, kWave);
-    if (lane == 0 && runs) atomicAdd(&w.ctl->runs, runs);
+    if (lane == 0 && runs) atomicAdd(&s_runs, runs);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_runs) atomicAdd(&w.ctl->runs, s_runs);  // one global atomic per workgroup
   }
 }
 
@@ -1379,6 +1387,8 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
     Work w = w0;
     w.group_log2 = group_log2_level(w0.group_log2, lev, seg_off != nullptr);
     const uint32_t glog_small = group_log2_small(w0.group_log2, lev, seg_off != nullptr);
+    // the first level of a plain sort with more levels counts its runs for the next plan
+    const int runs = (lev == 0 && levels > 1 && !seg_off) ? 1 : 0;
     const uint32_t tile_log2 = (t.tile_log2 == 12 || std::min(w.group_log2, glog_small ? glog_small : 99u) < 13) ? 12 : 13;
     const uint64_t groups_max = (n >> (glog_small ? glog_small : w.group_log2)) + w.big_max + 1;
     const int dst = lev & 1;
@@ -1417,14 +1427,14 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
     }
     if (tile_log2 == 12) {
       if (lev == 0)
-        RS_LAUNCH((k_scatter<K, F32, true, PAY, 512, 8>), gs_sc, 512, st, w, (int)lev, kin, pay_in, src, dst);
+        RS_LAUNCH((k_scatter<K, F32, true, PAY, 512, 8>), gs_sc, 512, st, w, (int)lev, kin, pay_in, src, dst, runs);
       else
-        RS_LAUNCH((k_scatter<K, false, false, PAY, 512, 8>), gs_sc, 512, st, w, (int)lev, kin, pay_in, src, dst);
+        RS_LAUNCH((k_scatter<K, false, false, PAY, 512, 8>), gs_sc, 512, st, w, (int)lev, kin, pay_in, src, dst, 0);
     } else {
       if (lev == 0)
-        RS_LAUNCH((k_scatter<K, F32, true, PAY, 1024, 8>), gs_sc, 1024, st, w, (int)lev, kin, pay_in, src, dst);
+        RS_LAUNCH((k_scatter<K, F32, true, PAY, 1024, 8>), gs_sc, 1024, st, w, (int)lev, kin, pay_in, src, dst, runs);
       else
-        RS_LAUNCH((k_scatter<K, false, false, PAY, 1024, 8>), gs_sc, 1024, st, w, (int)lev, kin, pay_in, src, dst);
+        RS_LAUNCH((k_scatter<K, false, false, PAY, 1024, 8>), gs_sc, 1024, st, w, (int)lev, kin, pay_in, src, dst, 0);
     }
     RS_LAUNCH(k_level_end, grid_for((w.big_max * kMaxK + 255) / 256, 4), 256, st, w, (int)lev, cap, target,
               last ? 1 : 0, (uint32_t)(dst + 1), ff, levels - lev - 1, cmin);
