@@ -1012,7 +1012,8 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
       if (tl + 1 < t_end) load_tile(tl + 1);
       // the first level classifies; later ones read the count pass's ids
       if constexpr (SRC_IN)
-        classify_batch<K, ITEMS>(tk, ti, bs.logk, key, valid, [&](int i) -> uint32_t { return idx[i]; }, b, pairs);
+        classify_batch<K, ITEMS>(tk, ti, bs.logk, key, valid, [&](int i) -> uint32_t { return idx[i]; }, b,
+                                 pairs);
       // rank inside (tile, bucket): one LDS atomic per element, or one per wave
       // when the whole wave falls into a single bucket (skewed inputs).  A
       // wave's valid elements are a prefix of its lanes, so lane 0 holds one
@@ -1070,9 +1071,10 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
         if constexpr (PAY) asm volatile("" ::"v"(npay[i]));
         if constexpr (!SRC_IN) asm volatile("" ::"v"(nb[i]));
       }
-      if (cnt == TILE) {
+      if (!PAY && cnt == TILE) {
         // a full tile: all staged reads, then all run offsets, then the
         // stores, so that no thread waits on one LDS round trip per element
+        // (not with a payload: its instances have no registers to spare)
         uint32_t sb[ITEMS], si[ITEMS];
         K sk[ITEMS];
 #pragma unroll
