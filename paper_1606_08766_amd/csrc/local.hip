@@ -131,7 +131,8 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
 // order; a word's rank is then the start of its bin plus the number of smaller
 // words inside the bin, found by comparing against the bin's words only.  On
 // the key distributions the sample sort leaves in a final segment (near
-// uniform over its range) a bin holds about 3 to 8 words, so this takes far
+// uniform over its range) a bin holds about 3 to 8 words (up to 16 in the
+// instances of at most 4096 words), so this takes far
 // fewer steps than a merge sort's log2(len) rounds.  The ranking costs about
 // the sum over the bins of size^2 compares; where that exceeds kRankBudget per
 // word (runs of equal keys, keys clustered far apart) the segment is left to
@@ -264,9 +265,10 @@ __global__ __launch_bounds__(THREADS, (THREADS >= 1024 ? 8 : 1)) void k_local_wo
   constexpr uint64_t SLOT = (1ull << PB) - 1;
   constexpr int XB = PAY ? PB : 0;  // slot bits kept in exact words (payload gather)
   // bins: about four words each in a full segment, for segments long
-  // enough to need them
+  // enough to need them; eight in the instances of at most 4096 words, whose
+  // LDS then still fits three workgroups per CU
   constexpr bool BINS = !MERGE && N >= 1024;
-  constexpr int LB = 31 - __builtin_clz((unsigned)(N / 4));
+  constexpr int LB = 31 - __builtin_clz((unsigned)(N <= 4096 ? N / 8 : N / 4));
   // the merge sort and the output read words as two halves (lo, hi); the
   // bins see the same memory as whole words
   __shared__ uint64_t s_words[NP];
