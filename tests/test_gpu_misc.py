@@ -88,6 +88,23 @@ def test_three_levels_match_oracle(dist):
     assert same_bits(host(ko), ek) and np.array_equal(host(po), ep)
 
 
+def test_three_levels_short_runs_match_oracle():
+    """Capacity 128 and target 64 leave 2^26 + 777 uniform keys three levels
+    of 128 buckets; the first level's runs (8192-key tiles over 128 buckets,
+    64 keys each) are short, so the later levels take the smaller tile groups
+    the plan chooses on the device.  The output equals the oracle's."""
+    n = (1 << 26) + 777
+    x = gen.keys("u64", "uniform", n, seed=6)
+    ek, ep, _ = O.sort(x, threads=8)
+    with R.tuned(cap=128, target=64):
+        ws = torch.empty(R.plain_workspace_bytes(R.U64, n), dtype=torch.uint8, device="cuda")
+        banner("three levels, short runs")
+        ko, po = R.sort(dev(x), workspace=ws)
+        st = R.stats(ws)
+    assert st["status"] == 0 and st["levels"] == 3 and st["oversize"] >= 0
+    assert same_bits(host(ko), ek) and np.array_equal(host(po), ep)
+
+
 def _golden_rank_error():
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", "median_tree_rank_error.txt")
