@@ -45,6 +45,23 @@ def test_plain_wide_range_duplicates(n, kt):
     assert np.array_equal(po, ep)
 
 
+@pytest.mark.parametrize("kt", ["u64", "u32"])
+@pytest.mark.parametrize("block_log2", [12, 15])
+def test_plain_tied_and_untied_blocks(kt, block_log2):
+    """Blocks of 2^block_log2 equal keys alternate with blocks of random keys,
+    so the waves of the count and scatter passes move in and out of the
+    classification mode that skips the key-only descent after a tile in which
+    every key tied a splitter key.  Both modes compute the same bucket; the
+    output equals the oracle's."""
+    n = (1 << 24) + 11
+    x = gen.keys(kt, "uniform", n, seed=21 + block_log2)
+    blocks = (np.arange(n) >> block_log2) & 1
+    x[blocks == 1] = x.dtype.type(12345)
+    ko, po = gpu_sort(x)
+    ek, ep, _ = O.sort(x, threads=8)
+    assert same_bits(ko, ek) and np.array_equal(po, ep)
+
+
 def test_plain_keys_only_and_empty():
     x = gen.keys("u64", "uniform", 100000, seed=5)
     ko, po = gpu_sort(x, with_perm=False)
