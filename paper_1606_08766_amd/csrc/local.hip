@@ -398,31 +398,83 @@ __global__ __launch_bounds__(THREADS, (THREADS >= 1024 ? 8 : 1)) void k_local_wo
     }
     __syncthreads();
     bool bad = false;
-    for (uint32_t j = tid; j < f.len; j += THREADS) {
-      const int qq = lpad(j);
-      const uint64_t cj = ((uint64_t)s_hi[qq] << 32) | s_lo[qq];
-      const uint32_t slot = (uint32_t)(cj & SLOT);
-      uint32_t idx;
-      K key;
-      if (exact) {
-        idx = (uint32_t)(cj >> XB);
-        key = (K)(mn + (K)(cj >> sh));
-      } else {
-        idx = idx_at(slot);
-        key = drop ? key_at(slot) : (K)(mn + (K)(cj >> sh));
-        if (check && j + 1 < f.len) {
-          const int qn = lpad(j + 1);
-          const uint64_t cn = ((uint64_t)s_hi[qn] << 32) | s_lo[qn];
-          if ((cn >> PB) == (cj >> PB)) {
-            // equal prefixes: the pair order decides
-            const uint32_t sn = (uint32_t)(cn & SLOT);
-            if (pair_less(key_at(sn), idx_at(sn), key, idx)) bad = true;
+    if constexpr (!PAY) {
+      for (uint32_t j = tid; j < f.len; j += THREADS) {
+        const int qq = lpad(j);
+        const uint64_t cj = ((uint64_t)s_hi[qq] << 32) | s_lo[qq];
+        const uint32_t slot = (uint32_t)(cj & SLOT);
+        uint32_t idx;
+        K key;
+        if (exact) {
+          idx = (uint32_t)(cj >> XB);
+          key = (K)(mn + (K)(cj >> sh));
+        } else {
+          idx = idx_at(slot);
+          key = drop ? key_at(slot) : (K)(mn + (K)(cj >> sh));
+          if (check && j + 1 < f.len) {
+            const int qn = lpad(j + 1);
+            const uint64_t cn = ((uint64_t)s_hi[qn] << 32) | s_lo[qn];
+            if ((cn >> PB) == (cj >> PB)) {
+              // equal prefixes: the pair order decides
+              const uint32_t sn = (uint32_t)(cn & SLOT);
+              if (pair_less(key_at(sn), idx_at(sn), key, idx)) bad = true;
+            }
+          }
+        }
+        keys_out[f.start + j] = to_output<K, F32>(key);
+        if (perm_out) perm_out[f.start + j] = idx;
+      }
+    } else {
+      // with a payload, gathered by slot from global memory: the thread's
+      // sorted elements j = tid + k * THREADS are read (LDS, and the global
+      // key and payload reads by slot) before any output store, since a load
+      // issued after stores waits for them
+      K okey[ITEMS];
+      uint32_t oidx[ITEMS], opay[ITEMS];
+#pragma unroll
+      for (int k = 0; k < ITEMS; k++) {
+        const uint32_t j = tid + k * THREADS;
+        okey[k] = K(0);
+        oidx[k] = 0;
+        opay[k] = 0;
+        if (j < f.len) {
+          const int qq = lpad(j);
+          const uint64_t cj = ((uint64_t)s_hi[qq] << 32) | s_lo[qq];
+          const uint32_t slot = (uint32_t)(cj & SLOT);
+          if (exact) {
+            oidx[k] = (uint32_t)(cj >> XB);
+            okey[k] = (K)(mn + (K)(cj >> sh));
+          } else {
+            oidx[k] = idx_at(slot);
+            okey[k] = drop ? key_at(slot) : (K)(mn + (K)(cj >> sh));
+          }
+          opay[k] = srcp[f.start + slot];
+        }
+      }
+      if (check) {  // uniform
+#pragma unroll
+        for (int k = 0; k < ITEMS; k++) {
+          const uint32_t j = tid + k * THREADS;
+          if (j + 1 < f.len) {
+            const uint64_t cj = ((uint64_t)s_hi[lpad(j)] << 32) | s_lo[lpad(j)];
+            const uint64_t cn = ((uint64_t)s_hi[lpad(j + 1)] << 32) | s_lo[lpad(j + 1)];
+            if ((cn >> PB) == (cj >> PB)) {
+              // equal prefixes: the pair order decides
+              const uint32_t sn = (uint32_t)(cn & SLOT);
+              if (pair_less(key_at(sn), idx_at(sn), okey[k], oidx[k])) bad = true;
+            }
           }
         }
       }
-      keys_out[f.start + j] = to_output<K, F32>(key);
-      if (perm_out) perm_out[f.start + j] = idx;
-      if constexpr (PAY) pay_out[f.start + j] = srcp[f.start + slot];
+#pragma unroll
+      for (int k = 0; k < ITEMS; k++) {
+        const uint32_t j = tid + k * THREADS;
+        if (j < f.len) {
+          keys_out[f.start + j] = to_output<K, F32>(okey[k]);
+          if (perm_out) perm_out[f.start + j] = oidx[k];
+          pay_out[f.start + j] = opay[k];
+        }
+      }
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) w.cls[cc][q].src = f.src | kPairsFlag;
   });
