@@ -114,11 +114,31 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(Work w, int cls, const K
       if constexpr (PAY) s_p[q] = p[i];
     }
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < f.len; j += THREADS) {
-      const int q = lpad(j);
-      keys_out[f.start + j] = to_output<K, F32>(sa.key(q));
-      if (perm_out) perm_out[f.start + j] = s_v[q];
-      if constexpr (PAY) pay_out[f.start + j] = srcp[f.start + s_p[q]];
+    if constexpr (PAY) {
+      // the payloads are gathered before any output store (a load issued
+      // after stores waits for them)
+      uint32_t pv[ITEMS];
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        const uint32_t j = i * THREADS + threadIdx.x;
+        pv[i] = j < f.len ? srcp[f.start + s_p[lpad(j)]] : 0u;
+      }
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        const uint32_t j = i * THREADS + threadIdx.x;
+        if (j < f.len) {
+          const int q = lpad(j);
+          keys_out[f.start + j] = to_output<K, F32>(sa.key(q));
+          if (perm_out) perm_out[f.start + j] = s_v[q];
+          pay_out[f.start + j] = pv[i];
+        }
+      }
+    } else {
+      for (uint32_t j = threadIdx.x; j < f.len; j += THREADS) {
+        const int q = lpad(j);
+        keys_out[f.start + j] = to_output<K, F32>(sa.key(q));
+        if (perm_out) perm_out[f.start + j] = s_v[q];
+      }
     }
     __syncthreads();
   });

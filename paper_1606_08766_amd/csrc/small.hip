@@ -119,9 +119,11 @@ __global__ __launch_bounds__(THREADS) void k_rfis(Work w, int cls, const K* in_k
         key = x.k;
         idx = x.i;
       }
+      uint32_t pv = 0;  // loaded before the stores (a load issued after stores waits for them)
+      if constexpr (PAY) pv = srcp[f.start + j];
       keys_out[f.start + r] = to_output<K, F32>(key);
       if (perm_out) perm_out[f.start + r] = idx;
-      if constexpr (PAY) pay_out[f.start + r] = srcp[f.start + j];
+      if constexpr (PAY) pay_out[f.start + r] = pv;
     }
     __syncthreads();
   }
@@ -404,9 +406,11 @@ __global__ __launch_bounds__(THREADS) void k_rquick(Work w, int cls, const K* in
     }
     // runs are now in wave order and globally sorted
     for (uint32_t r = threadIdx.x; r < n; r += THREADS) {
+      uint32_t pv = 0;  // loaded before the stores (a load issued after stores waits for them)
+      if constexpr (PAY) pv = srcp[f.start + bp[cur][r]];
       keys_out[f.start + r] = to_output<K, F32>(bk[cur][r]);
       if (perm_out) perm_out[f.start + r] = bv[cur][r];
-      if constexpr (PAY) pay_out[f.start + r] = srcp[f.start + bp[cur][r]];
+      if constexpr (PAY) pay_out[f.start + r] = pv;
     }
     __syncthreads();
   }
