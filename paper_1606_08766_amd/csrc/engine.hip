@@ -919,12 +919,65 @@ __device__ __forceinline__ uint32_t bins_excl_scan(uint32_t v, uint32_t* tmp) {
   return off + inc - v;
 }
 
+// Buckets of the finished level lev: split again or sort in LDS.  This reads
+// only the level's bucket bounds (offsets) and segment list, written before
+// its scatter, and writes only the next level's segment list, the class
+// lists and statistics, none of which the scatter reads; so the scatter's
+// workgroups do it first, each taking (segment, bucket) pairs first, first +
+// stride, ... of the m * kMaxK, instead of one more dependent launch.
+// Called by every thread of the block (route synchronizes it).
+struct LevelEnd {
+  uint32_t cap, target, last, dst_code, ff, left, cmin;
+};
+__device__ __forceinline__ void level_end(const Work& w, int lev, const LevelEnd& a, RouteLds& L, uint64_t first,
+                                          uint64_t stride) {
+  const int cur = lev & 1;
+  const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
+  const uint64_t total = (uint64_t)m * kMaxK;
+  for (uint64_t g0 = first; g0 < total; g0 += stride) {
+    const uint64_t g = g0 + threadIdx.x;
+    bool active = g < total;
+    const uint32_t s = active ? (uint32_t)(g / kMaxK) : 0u, b = (uint32_t)(g % kMaxK);
+    BigSeg bs{0, 0, 0, 1};
+    uint32_t len = 0, lo = 0;
+    if (active) {
+      bs = w.big[cur][s];
+      const uint32_t kk = 1u << bs.logk;
+      active = b < kk;
+      if (active) {
+        const uint32_t ng = w.group_base[s + 1] - w.group_base[s];
+        const uint32_t cb = w.count_base[s];
+        const uint32_t seg0 = w.offsets[cb];
+        lo = w.offsets[cb + b * ng] - seg0;
+        const uint32_t hi = (b + 1 < kk) ? w.offsets[cb + (b + 1) * ng] - seg0 : bs.len;
+        len = hi - lo;
+        if (lev == 0 && s == 0) w.ctl->l0_bucket[b] = len;
+      }
+    }
+    if (lev < kMaxLevels) {
+      // per-wave maximum and count, then one atomic per wave
+      uint32_t mx = len, nz = (active && len) ? 1u : 0u;
+      for (int d = kWave / 2; d > 0; d >>= 1) {
+        mx = max(mx, (uint32_t)__shfl_xor(mx, d, kWave));
+        nz += (uint32_t)__shfl_xor(nz, d, kWave);
+      }
+      if (lane_id() == 0) {
+        if (mx) atomicMax(&w.ctl->level_max[lev], mx);
+        if (nz) atomicAdd(&w.ctl->level_buckets[lev], nz);
+      }
+    }
+    active = active && len > 0;
+    route(w, L, &w.ctl->big_count[cur ^ 1], w.big[cur ^ 1], active, len > a.cap && !a.last, bs.start + lo, bs.ubase,
+          len, a.dst_code, a.cap, a.ff, a.target, a.left, a.cmin);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Scatter: classify, rank inside (tile, bucket), stage by bucket in LDS and
 // write each bucket's run contiguously to the destination buffer.
 template <typename K, bool F32, bool SRC_IN, bool PAY, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* in_keys, const uint32_t* in_pay,
-                                                     int src_buf, int dst_buf, int count_runs) {
+                                                     int src_buf, int dst_buf, int count_runs, LevelEnd le) {
   constexpr uint32_t TILE = THREADS * ITEMS;  // the host launches tiles no larger than a group
   const uint32_t GT = (1u << group_log2_of(w, lev)) / TILE;  // tiles per group
   static_assert(THREADS >= kMaxK, "one histogram bin per thread");
@@ -952,7 +1005,11 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
     sc.gb_end = 0;  // empty: forces a load
   }
   if (threadIdx.x < kMaxK) hist[threadIdx.x] = 0;
-  __syncthreads();
+  {
+    __shared__ RouteLds L;
+    route_lds_init(L);  // (its barrier also orders the stores above)
+    level_end(w, lev, le, L, (uint64_t)blockIdx.x * THREADS, (uint64_t)gridDim.x * THREADS);
+  }
 
   __shared__ uint32_t s_group;
   GroupQueue gq(w.ctl->queue[1], G);
@@ -1119,52 +1176,6 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
   }
 }
 
-// Buckets of the finished level: split again or sort in LDS.
-__global__ void k_level_end(Work w, int lev, uint32_t cap, uint32_t target, int last, uint32_t dst_code,
-                            uint32_t ff, uint32_t left, uint32_t cmin) {
-  const int cur = lev & 1;
-  const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
-  const uint64_t total = (uint64_t)m * kMaxK;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  __shared__ RouteLds L;
-  route_lds_init(L);
-  for (uint64_t g0 = (uint64_t)blockIdx.x * blockDim.x; g0 < total; g0 += stride) {
-    const uint64_t g = g0 + threadIdx.x;
-    bool active = g < total;
-    const uint32_t s = active ? (uint32_t)(g / kMaxK) : 0u, b = (uint32_t)(g % kMaxK);
-    BigSeg bs{0, 0, 0, 1};
-    uint32_t len = 0, lo = 0;
-    if (active) {
-      bs = w.big[cur][s];
-      const uint32_t kk = 1u << bs.logk;
-      active = b < kk;
-      if (active) {
-        const uint32_t ng = w.group_base[s + 1] - w.group_base[s];
-        const uint32_t cb = w.count_base[s];
-        const uint32_t seg0 = w.offsets[cb];
-        lo = w.offsets[cb + b * ng] - seg0;
-        const uint32_t hi = (b + 1 < kk) ? w.offsets[cb + (b + 1) * ng] - seg0 : bs.len;
-        len = hi - lo;
-        if (lev == 0 && s == 0) w.ctl->l0_bucket[b] = len;
-      }
-    }
-    if (lev < kMaxLevels) {
-      // per-wave maximum and count, then one atomic per wave
-      uint32_t mx = len, nz = (active && len) ? 1u : 0u;
-      for (int d = kWave / 2; d > 0; d >>= 1) {
-        mx = max(mx, (uint32_t)__shfl_xor(mx, d, kWave));
-        nz += (uint32_t)__shfl_xor(nz, d, kWave);
-      }
-      if (lane_id() == 0) {
-        if (mx) atomicMax(&w.ctl->level_max[lev], mx);
-        if (nz) atomicAdd(&w.ctl->level_buckets[lev], nz);
-      }
-    }
-    active = active && len > 0;
-    route(w, L, &w.ctl->big_count[cur ^ 1], w.big[cur ^ 1], active, len > cap && !last, bs.start + lo, bs.ubase,
-          len, dst_code, cap, ff, target, left, cmin);
-  }
-}
 
 // ===========================================================================
 // Host side
@@ -1396,6 +1407,8 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
     const int dst = lev & 1;
     const int src = (lev + 1) & 1;  // buffer written by the previous level
     const bool last = lev + 1 == levels;
+    // the level's buckets are routed by the scatter's workgroups (level_end)
+    const LevelEnd le{cap, target, last ? 1u : 0u, (uint32_t)(dst + 1), ff, levels - lev - 1, cmin};
     if (lev > 0 || seg_off) RS_LAUNCH(k_plan, 1, kPlanThreads, st, w, (int)lev, glog_small);  // level 0 of a plain sort: planned at the start
     const uint32_t gs = grid_for(w.big_max, 4);
     if (lev == 0) {
@@ -1429,17 +1442,15 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
     }
     if (tile_log2 == 12) {
       if (lev == 0)
-        RS_LAUNCH((k_scatter<K, F32, true, PAY, 512, 8>), gs_sc, 512, st, w, (int)lev, kin, pay_in, src, dst, runs);
+        RS_LAUNCH((k_scatter<K, F32, true, PAY, 512, 8>), gs_sc, 512, st, w, (int)lev, kin, pay_in, src, dst, runs, le);
       else
-        RS_LAUNCH((k_scatter<K, false, false, PAY, 512, 8>), gs_sc, 512, st, w, (int)lev, kin, pay_in, src, dst, 0);
+        RS_LAUNCH((k_scatter<K, false, false, PAY, 512, 8>), gs_sc, 512, st, w, (int)lev, kin, pay_in, src, dst, 0, le);
     } else {
       if (lev == 0)
-        RS_LAUNCH((k_scatter<K, F32, true, PAY, 1024, 8>), gs_sc, 1024, st, w, (int)lev, kin, pay_in, src, dst, runs);
+        RS_LAUNCH((k_scatter<K, F32, true, PAY, 1024, 8>), gs_sc, 1024, st, w, (int)lev, kin, pay_in, src, dst, runs, le);
       else
-        RS_LAUNCH((k_scatter<K, false, false, PAY, 1024, 8>), gs_sc, 1024, st, w, (int)lev, kin, pay_in, src, dst, 0);
+        RS_LAUNCH((k_scatter<K, false, false, PAY, 1024, 8>), gs_sc, 1024, st, w, (int)lev, kin, pay_in, src, dst, 0, le);
     }
-    RS_LAUNCH(k_level_end, grid_for((w.big_max * kMaxK + 255) / 256, 4), 256, st, w, (int)lev, cap, target,
-              last ? 1 : 0, (uint32_t)(dst + 1), ff, levels - lev - 1, cmin);
   }
 
   // final segments by size class (a class can only be non-empty if its lower
