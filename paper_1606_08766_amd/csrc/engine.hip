@@ -67,6 +67,12 @@ __device__ __forceinline__ uint32_t logk_for(uint32_t len, uint32_t target, uint
 
 __device__ __forceinline__ void set_status(Ctl* ctl, int32_t code) { atomicCAS(&ctl->status, 0, code); }
 
+// A compile-time flag passed to a generic lambda.
+template <bool B>
+struct BoolC {
+  static constexpr bool value = B;
+};
+
 // A value the caller knows to be the same in every lane (read from LDS, say),
 // moved to a scalar register.
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -269,10 +275,13 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev, uint32_t
 // depth d, index q = t - 2^d within its depth, holds splitter number
 // (2q+1) * 2^(logk-1-d) (1-based, in sorted order).
 constexpr uint32_t kSplRankBudget = 64;  // compares per sample the ranking path may take
+// first-level bucket ids when at least 1 / kDupIdsDiv of the splitter keys
+// equal their predecessor
+constexpr uint32_t kDupIdsDiv = 16;
 
 template <typename K, bool F32, bool SRC_IN, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K* in_keys, int src_buf,
-                                                       uint32_t a, uint64_t seed) {
+                                                       uint32_t a, uint64_t seed, int ids_ok) {
   constexpr int N = THREADS * ITEMS;
   constexpr int NP = lpad_size(N);
   constexpr int LB = 31 - __builtin_clz((unsigned)(N / 8));  // bins of the ranking path
@@ -284,6 +293,8 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
   __shared__ uint32_t s_bin[(1 << LB) + 1];
   __shared__ uint32_t s_red[6 * (THREADS / kWave)];
   __shared__ uint32_t s_cost;
+  __shared__ K s_spl[kMaxK];  // level 0, segment 0: the sorted splitter keys
+  __shared__ uint32_t s_dup;
   const LdsArr<K> sa{s_lo, s_hi, s_v, nullptr};
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
@@ -414,6 +425,7 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
               if (lev == 0 && s == 0) {
                 w.ctl->l0_spl_key[j - 1] = (uint64_t)key;
                 w.ctl->l0_spl_pos[j - 1] = idx;
+                s_spl[j - 1] = key;
               }
             }
           }
@@ -437,10 +449,25 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
         for (uint32_t j = threadIdx.x + 1; j < kk; j += THREADS) {
           w.ctl->l0_spl_key[j - 1] = (uint64_t)sa.key(lpad(j * ae - 1u));
           w.ctl->l0_spl_pos[j - 1] = s_v[lpad(j * ae - 1u)];
+          s_spl[j - 1] = sa.key(lpad(j * ae - 1u));
         }
       }
     }
     if (lev == 0 && s == 0 && threadIdx.x == 0) w.ctl->l0_k = kk;
+    if (lev == 0 && m == 1 && ids_ok) {  // uniform
+      // Keys that tie a splitter cost the (key, position) descent.  When the
+      // one first-level segment's splitters repeat keys (few distinct keys),
+      // its count stores each key's bucket for the scatter, which then
+      // skips the second classification; otherwise the scatter classifies
+      // again, cheaper than writing and reading the ids.
+      if (threadIdx.x == 0) s_dup = 0;
+      __syncthreads();
+      uint32_t d = 0;
+      for (uint32_t j = threadIdx.x + 1; j + 1 < kk; j += THREADS) d += s_spl[j] == s_spl[j - 1] ? 1u : 0u;
+      if (d) atomicAdd(&s_dup, d);
+      __syncthreads();
+      if (threadIdx.x == 0) w.ctl->ids0 = s_dup * kDupIdsDiv >= kk ? 1u : 0u;
+    }
     __syncthreads();
   }
 }
@@ -650,6 +677,9 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
   const uint32_t G = w.ctl->total_groups;
   const BufView<K> bv{SRC_IN ? nullptr : w.buf_rec[src_buf]};
+  // bucket ids for the scatter: always on a level that reads a buffer; on
+  // the first level when its splitters chose so (ids0)
+  const bool put_ids = !SRC_IN || (w.ids != nullptr && w.ctl->ids0 != 0u);
   const uint32_t lane = lane_id();
   if (threadIdx.x == 0) {
     sc.gb = 1;
@@ -709,7 +739,7 @@ __global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_
                                    return bv.idx(pos);
                                },
                                b, pairs);
-      if constexpr (!SRC_IN) {
+      if (put_ids) {
 #pragma unroll
         for (int i = 0; i < ITEMS; i++)
           if (valid[i]) put_bucket_id(w.ids, sstart, (uint64_t)tl * TILE + place(i), slogk, b[i]);
@@ -999,6 +1029,10 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
   const uint32_t* bpay = SRC_IN ? in_pay : w.buf_pay[src_buf];
   const BufView<K> dv{w.buf_rec[dst_buf]};
   uint32_t* dpay = w.buf_pay[dst_buf];
+  // the first level reads the count pass's bucket ids when it stored them
+  // (see k_count), loaded before any store; the host allows first-level ids
+  // only for calls without a payload
+  const bool ids0 = SRC_IN && !PAY && w.ids != nullptr && w.ctl->ids0 != 0u;
   const uint32_t lane = lane_id();
   if (threadIdx.x == 0) {
     sc.gb = 1;
@@ -1026,6 +1060,11 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
     uint64_t run_off = 0;
     if (threadIdx.x < kk) run_off = sc.start + (uint64_t)(w.offsets[sc.cb + threadIdx.x * ng + gl] - sc.seg0);
     const BigSeg bs{sc.start, sc.ubase, sc.len, sc.logk};
+    // The group's tiles, in one of two compiled forms: IDS, reading each
+    // element's bucket from the count pass (every level that reads a buffer,
+    // and the first level when it stored them), or classifying again.
+    auto tiles = [&](auto ids_c) {
+    constexpr bool IDS = !SRC_IN || decltype(ids_c)::value;
     // the group's tiles are loaded one ahead: the loads of tile tl + 1 are in
     // flight while tile tl is classified, ranked and written
     K nkey[ITEMS];
@@ -1044,6 +1083,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
           if constexpr (SRC_IN) {
             nkey[i] = in_keys[base + jj];  // raw bits: mapped when the tile is used, so the prefetch does not wait
             nidx[i] = (uint32_t)(base + jj - bs.ubase);
+            if constexpr (IDS) nb[i] = get_bucket_id(w.ids, bs.start, (uint64_t)tl * TILE + jj, bs.logk);
           } else {
             bv.get(base + jj, nkey[i], nidx[i]);
             nb[i] = get_bucket_id(w.ids, bs.start, (uint64_t)tl * TILE + jj, bs.logk);
@@ -1067,8 +1107,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
         b[i] = nb[i];
       }
       if (tl + 1 < t_end) load_tile(tl + 1);
-      // the first level classifies; later ones read the count pass's ids
-      if constexpr (SRC_IN)
+      if constexpr (!IDS)
         classify_batch<K, ITEMS>(tk, ti, bs.logk, key, valid, [&](int i) -> uint32_t { return idx[i]; }, b,
                                  pairs);
       // rank inside (tile, bucket): one LDS atomic per element, or one per wave
@@ -1126,7 +1165,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
       for (int i = 0; i < ITEMS; i++) {
         asm volatile("" ::"v"(nkey[i]), "v"(nidx[i]));
         if constexpr (PAY) asm volatile("" ::"v"(npay[i]));
-        if constexpr (!SRC_IN) asm volatile("" ::"v"(nb[i]));
+        if constexpr (IDS) asm volatile("" ::"v"(nb[i]));
       }
       if (!PAY && cnt == TILE) {
         // a full tile: all staged reads, then all run offsets, then the
@@ -1162,6 +1201,11 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int lev, const K* i
       }
       __syncthreads();
     }
+    };
+    if (ids0)
+      tiles(BoolC<true>{});
+    else
+      tiles(BoolC<false>{});
   }
   // the first level's run count, read by the next level's plan (a kernel
   // argument: a load here would wait for the write-out stores first)
@@ -1416,11 +1460,14 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
       // one-workgroup sample sort: 16 samples per bucket keep its buckets
       // within twice the target while halving that step
       const uint32_t a0 = cmin ? std::min<uint32_t>(a, 16u) : a;
+      // first-level bucket ids need the id buffer (two levels or more) and
+      // are not taken by the payload scatter
+      const int ids_ok = (w.ids != nullptr && !PAY) ? 1 : 0;
       RS_LAUNCH((k_splitters<K, F32, true, kSplThreads, kSplItems>), gs, kSplThreads, st, w, (int)lev, kin, src, a0,
-                t.seed);
+                t.seed, ids_ok);
     } else {
       RS_LAUNCH((k_splitters<K, false, false, kSplThreads, kSplItems>), gs, kSplThreads, st, w, (int)lev, kin, src, a,
-                t.seed);
+                t.seed, 0);
     }
     // count tiles: 512 threads x 8 keys; scatter tiles: 512 x 8 (tile_log2
     // 12) or 1024 x 8 (tile_log2 13); both walk the same groups of

@@ -105,6 +105,36 @@ def test_three_levels_short_runs_match_oracle():
     assert same_bits(host(ko), ek) and np.array_equal(host(po), ep)
 
 
+@pytest.mark.parametrize("kt,dist,n,tune", [
+    ("u64", "zero", (1 << 22) + 333, {}),
+    ("u32", "deterdupl", (1 << 22) + 333, {}),
+    ("f32", "topbits", (1 << 22) + 333, {}),
+    # 2^18 buckets of 64 keys over two levels: 512 first-level buckets, two-byte ids
+    ("u32", "deterdupl", (1 << 24) - 5, dict(cap=128, target=64)),
+])
+def test_first_level_bucket_ids_match_oracle(kt, dist, n, tune):
+    """Inputs of few distinct keys repeat splitter keys, so the first level's
+    count pass stores every key's bucket and its scatter reads them instead of
+    classifying again (taken when at least 1/16 of the splitter keys equal
+    their predecessor).  The splitters show that rule holds, and the output
+    equals the oracle's."""
+    x = gen.keys(kt, dist, n, seed=n % 1000 + 4, param=3 if dist == "topbits" else 0)
+    ek, ep, _ = O.sort(x, threads=8)
+    kty = R.KT_OF_DTYPE[torch.from_numpy(x[:0]).dtype]
+    with R.tuned(**tune):
+        ws = torch.empty(R.plain_workspace_bytes(kty, n), dtype=torch.uint8, device="cuda")
+        banner("first-level bucket ids %s %s %d" % (kt, dist, n))
+        ko, po = R.sort(dev(x), workspace=ws)
+        st = R.stats(ws)
+    assert st["status"] == 0 and st["levels"] == 2
+    if tune:
+        assert st["k"] == 512
+    sk = st["splitter_keys"]
+    dup = int(np.count_nonzero(sk[1:] == sk[:-1]))
+    assert dup * 16 >= st["k"]
+    assert same_bits(host(ko), ek) and np.array_equal(host(po), ep)
+
+
 def _golden_rank_error():
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", "median_tree_rank_error.txt")
