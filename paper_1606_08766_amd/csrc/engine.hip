@@ -184,12 +184,36 @@ __global__ void k_init(Work w, const uint64_t* seg_off, uint32_t num_segs, uint6
   }
 }
 
+// The splitter kernel's shape: up to kSplThreads * kSplItems samples per segment.
+constexpr int kSplThreads = 1024, kSplItems = 8;  // (a = 32 at k = 256, 16 at 512)
+constexpr uint32_t kStartThreads = 256;
+
 // A plain sort's start in one launch: reset the control block, route the one
 // segment [0, n) (split it, or sort it in its class), and plan level 0 when
 // it is split (one segment: its tile groups and count-matrix base are
-// immediate).
-__global__ __launch_bounds__(64) void k_start_plain(Work w, uint64_t n, uint32_t cap, uint32_t target,
-                                                   uint32_t levels, uint32_t ff, uint32_t cmin) {
+// immediate).  With `staged` (a split sort of at least kSplThreads *
+// kSplItems keys), the workgroups also draw the first level's sample, the
+// same a0 * k positions the splitter kernel would, and store the (raw key,
+// position) records at the front of buffer B, which the first level does
+// not touch before its scatter: the random loads are spread over many CUs
+// instead of coming from the splitter kernel's one workgroup.
+template <typename K>
+__global__ __launch_bounds__(kStartThreads) void k_start_plain(Work w, uint64_t n, uint32_t cap, uint32_t target,
+                                                              uint32_t levels, uint32_t ff, uint32_t cmin,
+                                                              const K* in_keys, uint32_t a0, uint64_t seed,
+                                                              int staged) {
+  if (staged) {
+    const uint32_t logk = logk_for((uint32_t)n, target, levels, w.spread);
+    const uint32_t S = min(a0, (uint32_t)(kSplThreads * kSplItems) >> logk) << logk;
+    const uint32_t j = blockIdx.x * kStartThreads + threadIdx.x;
+    if (j < S) {
+      // level 0, segment start 0: the stream and position of k_splitters
+      const uint64_t r = rand_at(seed, 0ull, j);
+      const uint64_t pos = ((r >> 32) * n) >> 32;
+      BufView<K>{w.buf_rec[1]}.put(j, in_keys[pos], (uint32_t)pos);
+    }
+    if (blockIdx.x != 0) return;
+  }
   uint32_t* p = reinterpret_cast<uint32_t*>(w.ctl);
   const uint32_t nw = (uint32_t)(offsetof(Ctl, l0_spl_key) / 4);
   for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) p[i] = (i == 1) ? levels : 0u;
@@ -281,7 +305,7 @@ constexpr uint32_t kDupIdsDiv = 16;
 
 template <typename K, bool F32, bool SRC_IN, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K* in_keys, int src_buf,
-                                                       uint32_t a, uint64_t seed, int ids_ok) {
+                                                       uint32_t a, uint64_t seed, int ids_ok, int staged) {
   constexpr int N = THREADS * ITEMS;
   constexpr int NP = lpad_size(N);
   constexpr int LB = 31 - __builtin_clz((unsigned)(N / 8));  // bins of the ranking path
@@ -310,7 +334,10 @@ __global__ __launch_bounds__(THREADS) void k_splitters(Work w, int lev, const K*
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = threadIdx.x * ITEMS + i;
-      if (j < S) {
+      if (SRC_IN && staged && j < S) {
+        // drawn by k_start_plain (the same positions), stored in order
+        BufView<K>{w.buf_rec[1]}.get(j, k[i], v[i]);
+      } else if (j < S) {
         const uint64_t r = rand_at(seed, ((uint64_t)lev << 40) ^ bs.start, j);
         const uint64_t pos = bs.start + (((r >> 32) * (uint64_t)bs.len) >> 32);
         if constexpr (SRC_IN) {
@@ -1386,7 +1413,6 @@ static inline uint32_t grid_for(uint64_t work, uint32_t per_cu) {
 
 
 
-constexpr int kSplThreads = 1024, kSplItems = 8;  // up to 8192 samples (a = 32 at k = 256, 16 at 512)
 
 // Algorithm of each size class: RFIS, RQuick or the LDS merge sort.
 template <typename K, bool F32, bool PAY>
@@ -1430,8 +1456,15 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
     const uint32_t want = std::min<uint32_t>(2 * target, cap);
     while (cmin + 2 < (uint32_t)kNumClasses && h_class_max[cmin] < want) cmin++;
   }
+  // a single-level sort of few buckets (cmin > 0) is latency-bound on its
+  // one-workgroup sample sort: 16 samples per bucket keep its buckets
+  // within twice the target while halving that step
+  const uint32_t a0 = cmin ? std::min<uint32_t>(a, 16u) : a;
+  // the first level's sample drawn at the start (k_start_plain), room in buffer B
+  const int staged = (!seg_off && levels > 0 && n >= (uint64_t)kSplThreads * kSplItems) ? 1 : 0;
   if (!seg_off) {
-    RS_LAUNCH(k_start_plain, 1, 64, st, w, n, cap, target, levels, ff, cmin);
+    RS_LAUNCH(k_start_plain<K>, staged ? (uint32_t)(kSplThreads * kSplItems / kStartThreads) : 1u, kStartThreads,
+              st, w, n, cap, target, levels, ff, cmin, kin, a0, t.seed, staged);
   } else {
     RS_LAUNCH(k_reset, 1, 256, st, w.ctl, levels);
     RS_LAUNCH(k_init, grid_for((num_segs + 1023) / 1024, 1), 1024, st, w, seg_off, num_segs, n, cap, target, levels,
@@ -1456,18 +1489,14 @@ static int enqueue_typed(const void* keys_in, const uint32_t* pay_in, const uint
     if (lev > 0 || seg_off) RS_LAUNCH(k_plan, 1, kPlanThreads, st, w, (int)lev, glog_small);  // level 0 of a plain sort: planned at the start
     const uint32_t gs = grid_for(w.big_max, 4);
     if (lev == 0) {
-      // a single-level sort of few buckets (cmin > 0) is latency-bound on its
-      // one-workgroup sample sort: 16 samples per bucket keep its buckets
-      // within twice the target while halving that step
-      const uint32_t a0 = cmin ? std::min<uint32_t>(a, 16u) : a;
       // first-level bucket ids need the id buffer (two levels or more) and
       // are not taken by the payload scatter
       const int ids_ok = (w.ids != nullptr && !PAY) ? 1 : 0;
       RS_LAUNCH((k_splitters<K, F32, true, kSplThreads, kSplItems>), gs, kSplThreads, st, w, (int)lev, kin, src, a0,
-                t.seed, ids_ok);
+                t.seed, ids_ok, staged);
     } else {
       RS_LAUNCH((k_splitters<K, false, false, kSplThreads, kSplItems>), gs, kSplThreads, st, w, (int)lev, kin, src, a,
-                t.seed, 0);
+                t.seed, 0, 0);
     }
     // count tiles: 512 threads x 8 keys; scatter tiles: 512 x 8 (tile_log2
     // 12) or 1024 x 8 (tile_log2 13); both walk the same groups of
