@@ -124,6 +124,18 @@ def test_full_size_32bit_keys(kt, dist):
         assert O.rank(x, int(po[r])) == int(r)
 
 
+@pytest.mark.parametrize("kt,dist", [("u32", "deterdupl"), ("u32", "zero"), ("f32", "deterdupl")])
+def test_full_size_32bit_tied_keys(kt, dist):
+    """2^28 32-bit keys of 16 distinct values or all equal: the first level's
+    splitters repeat keys, so its count stores bucket ids for the scatter.
+    The output equals the closed form."""
+    n = 1 << 28
+    x = gen.keys(kt, dist, n, seed=3)
+    ko, po = gpu_sort(x)
+    ek, ep = closed_form(dist, n, dtype=np.float32 if kt == "f32" else np.uint32)
+    assert np.array_equal(ko, ek) and np.array_equal(po, ep)
+
+
 def test_repeat_calls_identical():
     x = gen.keys("u64", "gaussian", 3_000_000, seed=9)
     a = gpu_sort(x)
