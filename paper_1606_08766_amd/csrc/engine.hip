@@ -691,8 +691,13 @@ __device__ __forceinline__ void seg_for_group(const Work& w, int cur, uint32_t m
   __syncthreads();
 }
 
+// Occupancy: 32-bit keys fit eight waves per SIMD (at most 64 VGPRs); the
+// 64-bit instances spill at that bound and keep what the compiler chooses
+// (the first level's count got faster on tied keys but 2 us slower on the
+// latency path, the buffer level's slower on every input).
 template <typename K, bool F32, bool SRC_IN, int THREADS, int ITEMS>
-__global__ __launch_bounds__(THREADS) void k_count(Work w, int lev, const K* in_keys, int src_buf) {
+__global__ __launch_bounds__(THREADS, sizeof(K) == 4 ? 8 : 1) void k_count(Work w, int lev, const K* in_keys,
+                                                                          int src_buf) {
   constexpr uint32_t TILE = THREADS * ITEMS;
   static_assert(TILE <= (1u << kGroupMinLog2), "tiles divide a group");
   const uint32_t GT = (1u << group_log2_of(w, lev)) / TILE;  // tiles per group
