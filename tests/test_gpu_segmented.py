@@ -142,6 +142,19 @@ def test_single_big_segment_with_payload():
     check_against_oracle(keys, off, pay)
 
 
+@pytest.mark.parametrize("dist", ["deterdupl", "zero"])
+def test_one_split_segment_of_tied_keys_among_small_ones(dist):
+    """A keys-only call whose one segment above the LDS capacity (4M keys of
+    few distinct values, starting at an offset that is not a multiple of
+    anything) is split over two levels: its first level stores bucket ids at
+    the segment's own place in the id buffer.  Every segment equals the
+    oracle's."""
+    sizes = np.array([5, 700, 4_000_003, 64, 3000, 0, 1], np.uint64)
+    keys, _, off = gen.segmented("u64", sizes, ["uniform", "gaussian", dist, "uniform", "zero", "uniform", "reverse"],
+                                 seed=12)
+    check_against_oracle(keys, off)
+
+
 def test_all_empty_and_one_element():
     keys = np.array([7], dtype=np.uint64)
     off = np.array([0, 0, 0, 1, 1], dtype=np.uint64)
