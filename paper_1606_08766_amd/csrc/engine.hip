@@ -639,10 +639,12 @@ struct GroupQueue {
   }
   // Called by every thread; returns the next group, or hi when the share is
   // done.  The caller's group loop must pass a __syncthreads before the next
-  // call (slot is rewritten there).
+  // call (slot is rewritten there).  An empty share (a level with no work,
+  // as the host launches for a batch whose segments all fit the local sort)
+  // takes no atomic: a thousand workgroups on eight counters serialise.
   __device__ __forceinline__ uint32_t next(uint32_t* slot) {
     if (threadIdx.x == 0) {
-      const uint32_t g = lo + atomicAdd(ctr, 1u);
+      const uint32_t g = lo < hi ? lo + atomicAdd(ctr, 1u) : hi;
       *slot = g < hi ? g : hi;
     }
     __syncthreads();
