@@ -254,6 +254,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Work w, int lev, uint32_t
   const int cur = lev & 1;
   const uint32_t m = (uint32_t)min((uint64_t)w.ctl->big_count[cur], w.big_max);
   const BigSeg* B = w.big[cur];
+  // the first level of a segmented call: the class lists hold only the
+  // user segments routed so far (k_init); the levels append theirs after
+  if (lev == 0 && threadIdx.x < (unsigned)kNumClasses) w.ctl->class_in[threadIdx.x] = w.ctl->class_count[threadIdx.x];
   if (threadIdx.x == 0) {
     const uint32_t runs = w.ctl->runs;
     const bool short_runs = glog_small && runs && w.n / runs < kShortRun;

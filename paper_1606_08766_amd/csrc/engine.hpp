@@ -49,6 +49,7 @@ struct Ctl {
   uint32_t runs;                   // (tile, bucket) runs the first level's scatter wrote
   uint32_t glog;                   // log2 keys per tile group of the levels after the first (0: as planned)
   uint32_t ids0;                   // 1: the first level (one segment) passes bucket ids from count to scatter
+  uint32_t class_in[kNumClasses];  // segmented calls: user segments at the front of each class list
   uint32_t queue[2][8];            // per-XCD tile-group queues of the count and scatter passes
   uint32_t class_count[kNumClasses];  // final segments per size class (last = oversize)
   uint32_t level_max[kMaxLevels];  // largest bucket created per level

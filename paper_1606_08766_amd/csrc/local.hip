@@ -33,10 +33,20 @@ struct Shape {
 // loads.  body(cc, q) runs on every thread of the block.
 template <int THREADS, typename F>
 __device__ __forceinline__ void for_each_segment(const Work& w, int cls, uint32_t flag, uint32_t* s_list,
-                                                 uint32_t& s_n, F&& body) {
+                                                 uint32_t& s_n, F&& body, int part = 0) {
   if (!flag) {
-    const uint32_t cnt = final_count(w, cls);
-    for (uint32_t q = blockIdx.x; q < cnt; q += gridDim.x) body(cls, q);
+    // part 1 / 2: a mixed call's user segments / level segments.  k_init
+    // routes every user segment before any level runs, so they are the
+    // first class_in entries of each class list.
+    uint32_t q0 = 0, q1 = final_count(w, cls);
+    if (part && cls >= 0) {
+      const uint32_t nin = min(w.ctl->class_in[cls], q1);
+      if (part == 1)
+        q1 = nin;
+      else
+        q0 = nin;
+    }
+    for (uint32_t q = q0 + blockIdx.x; q < q1; q += gridDim.x) body(cls, q);
     return;
   }
   for (int cc = 0; cc <= kNumClasses - 2; cc++) {
@@ -497,7 +507,7 @@ __global__ __launch_bounds__(THREADS, (THREADS >= 1024 ? 8 : 1)) void k_local_wo
       }
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) w.cls[cc][q].src = f.src | kPairsFlag;
-  });
+  }, mixed ? (SRCBUF ? 2 : 1) : 0);
 }
 
 // ---------------------------------------------------------------------------
